@@ -1,0 +1,61 @@
+"""Assembly of the trace system K dU = R (section 2.2.1, eq. LS).
+
+Parity: pinned through the dense uncondensed solve (tests) and the
+closed-form block count nnzb = N_f + 30 E of a structured hex mesh.
+
+K is returned as a dict {(f, g): b x b block}; every element adds its 36
+face-pair blocks of K_e.  R = G + sum_e P_e^T r_e.
+"""
+import numpy as np
+
+
+def assemble(tmesh, Ks, rs, G):
+    b = tmesh.b
+    K = {}
+    for e in range(tmesh.n_elem):
+        fs = tmesh.elem_faces[e]
+        Ke = Ks[e]
+        for a in range(6):
+            for c in range(6):
+                blk = Ke[a * b:(a + 1) * b, c * b:(c + 1) * b]
+                key = (int(fs[a]), int(fs[c]))
+                K[key] = K[key] + blk if key in K else blk.copy()
+    R = np.array(G, dtype=np.float64, copy=True)
+    for e in range(tmesh.n_elem):
+        R[tmesh.element_dofs(e)] += rs[e]
+    return K, R
+
+
+def to_dense(tmesh, K):
+    b = tmesh.b
+    M = np.zeros((tmesh.n_trace, tmesh.n_trace))
+    for (f, g), blk in K.items():
+        M[f * b:(f + 1) * b, g * b:(g + 1) * b] = blk
+    return M
+
+
+def to_csr(tmesh, K):
+    import scipy.sparse as sp
+    return sp.csr_matrix(to_dense(tmesh, K)) if tmesh.n_trace <= 6000 else _bsr(tmesh, K)
+
+
+def _bsr(tmesh, K):
+    import scipy.sparse as sp
+    b = tmesh.b
+    keys = sorted(K.keys())
+    indptr = np.zeros(tmesh.n_face + 1, dtype=np.int64)
+    for f, _ in keys:
+        indptr[f + 1] += 1
+    indptr = np.cumsum(indptr)
+    indices = np.array([g for _, g in keys], dtype=np.int64)
+    data = np.stack([K[k] for k in keys])
+    return sp.bsr_matrix((data, indices, indptr),
+                         shape=(tmesh.n_trace, tmesh.n_trace)).tocsr()
+
+
+def matvec(tmesh, K, x):
+    b = tmesh.b
+    y = np.zeros(tmesh.n_trace)
+    for (f, g), blk in K.items():
+        y[f * b:(f + 1) * b] += blk @ x[g * b:(g + 1) * b]
+    return y

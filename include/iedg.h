@@ -1,0 +1,217 @@
+/*
+ * iedg.h -- C ABI of the MI355X (gfx950) library for the linear solve of one
+ * Newton step of an IEDG discretisation.
+ *
+ * Paper: Fernandez, Nguyen, Roca, Peraire, "Implicit large-eddy simulation
+ * of compressible flows using the Interior Embedded Discontinuous Galerkin
+ * method", section 2.2.  The Newton linear system of section 2.2.1 is
+ *
+ *     [ A  B ] [ dZ ]   [ F ]
+ *     [ C  D ] [ dU ] = [ G ]
+ *
+ * with A block diagonal (one dense block per element).  Eliminating dZ gives
+ * the trace system K dU = R, K = D - C A^{-1} B, R = G - C A^{-1} F (eq. LS),
+ * which is solved by restarted GMRES with iterated classical Gram-Schmidt,
+ * left-preconditioned by the zero-fill block ILU of K (section 2.2.2,
+ * eq. LS1).  dZ is then recovered element by element.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Sizes: n = local (q, u) dofs per element, b = trace dofs per face,
+ *   t = 6 b trace dofs per element (faces in local order -x,+x,-y,+y,-z,+z),
+ *   E elements, N_f faces, N_t = N_f b global trace dofs (dof f*b + l).
+ * - Every array argument is a DEVICE pointer owned by the caller unless the
+ *   argument says "host".  Dense element blocks are row-major and
+ *   element-major: X[e][row][col].  Global trace vectors are FP64 [N_t].
+ * - Calls enqueue work on the given HIP stream and return at once, except
+ *   where a call says it synchronises.  Argument errors are returned
+ *   immediately (nothing is enqueued).  Conditions detected on the device
+ *   (a zero or non-finite pivot) are latched in a device status word and
+ *   reported by iedg_sync_status().
+ * - The library may allocate device workspace on first use of a size
+ *   (GMRES basis, reduction buffers); later calls of the same or smaller
+ *   size do not allocate.
+ * - A context is not thread-safe; use one per host thread.
+ */
+#ifndef IEDG_H
+#define IEDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IEDG_OK = 0,
+  IEDG_ERR_INVALID_ARG = -1,   /* bad size, null pointer, aliasing, etc. */
+  IEDG_ERR_SINGULAR = -2,      /* zero / non-finite pivot met on the device */
+  IEDG_ERR_NOT_CONVERGED = -3, /* GMRES hit max_iters above tolerance */
+  IEDG_ERR_NONFINITE = -4,     /* NaN/Inf in a right-hand side or residual */
+  IEDG_ERR_OOM = -5,           /* workspace allocation failed */
+  IEDG_ERR_HIP = -6,           /* a HIP runtime call failed */
+  IEDG_ERR_UNSUPPORTED = -7    /* size or precision not built in */
+} iedg_status;
+
+/* Storage / arithmetic precision of factors and assembled blocks.
+ * IEDG_F64: FP64 storage and MFMA arithmetic.
+ * IEDG_F32: FP32 storage, FP32 MFMA with FP32 accumulation.
+ * IEDG_BF16: FP32 storage; trailing updates of the condensation take BF16
+ *            operands with FP32 accumulation (MFMA); panels stay FP32. */
+typedef enum { IEDG_F64 = 0, IEDG_F32 = 1, IEDG_BF16 = 2 } iedg_prec;
+
+typedef struct iedg_context_s* iedg_context;
+typedef struct iedg_mesh_s* iedg_mesh;
+
+/* ---- context ---------------------------------------------------------- */
+iedg_status iedg_create(iedg_context* out, int device);
+void iedg_destroy(iedg_context ctx);
+const char* iedg_last_error(iedg_context ctx);
+const char* iedg_status_string(iedg_status s);
+/* Synchronises `stream`, then returns and clears the device status word:
+ * IEDG_OK or IEDG_ERR_SINGULAR; *bad_index (may be NULL) receives the index
+ * of the first failing element (condense) or block row (factor_ilu0). */
+iedg_status iedg_sync_status(iedg_context ctx, hipStream_t stream, int64_t* bad_index);
+
+/* ---- trace mesh and block pattern ------------------------------------- */
+/* Builds the block sparsity pattern of K (a b x b block (f, g) exists iff
+ * faces f and g belong to a common element; section 2.2.1), the element ->
+ * BSR scatter map, the row ordering used by BILU(0) and its level sets
+ * (section 2.2.2), and copies them to the device.
+ * elem_faces: host [n_elem][6] face ids, local order -x,+x,-y,+y,-z,+z.
+ * ordering: 0 = greedy colouring (faces visited by ascending id, each takes
+ *   the smallest colour unused by an already coloured face sharing an
+ *   element; rows listed by (colour, face id)); 1 = natural face order;
+ *   2 = the permutation given in `order` (host [n_face]).
+ * BSR layout: block row i (0 <= i < n_face) is face order[i]; its blocks
+ * occupy slots row_ptr[i] .. row_ptr[i+1]-1, sorted by the position of their
+ * column face in the ordering (so lower blocks, the diagonal, then upper
+ * blocks).  A block is b*b contiguous values stored COLUMN-major (entry
+ * (r, c) at c*b + r). */
+iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face,
+                             int32_t face_dofs, const int32_t* elem_faces,
+                             int32_t ordering, const int32_t* order,
+                             iedg_mesh* out);
+void iedg_mesh_destroy(iedg_mesh mesh);
+
+typedef struct {
+  int64_t n_elem, n_face, face_dofs, n_trace, nnzb, n_levels;
+} iedg_mesh_info;
+/* Host outputs, each may be NULL: order [n_face], level_ptr [n_levels+1]
+ * (rows level_ptr[l] .. level_ptr[l+1]-1 of the ordering form level l),
+ * row_ptr [n_face+1], col_face [nnzb]. */
+iedg_status iedg_mesh_query(iedg_mesh mesh, iedg_mesh_info* info, int32_t* order,
+                            int32_t* level_ptr, int32_t* row_ptr, int32_t* col_face);
+
+/* ---- a1: element static condensation (section 2.2.1, eq. LS) ---------- */
+/* For every element, with the bordered matrix [A B F; C D 0]:
+ *   P A = L U (partial pivoting over the rows of A),
+ *   U12 = L^{-1} P B,  w = L^{-1} P F,  L21 = C U^{-1},
+ *   Ke = D - L21 U12 = D - C A^{-1} B,  r = -L21 w = -C A^{-1} F.
+ * Inputs (FP64, read only): A [E][n][n], B [E][n][t], C [E][t][n],
+ *   D [E][t][t], F [E][n] (F may be NULL: then w and r are not written).
+ * Outputs (element type given by prec: double for IEDG_F64, float
+ *   otherwise): LU [E][n][n] (unit-lower L below the diagonal, U on and
+ *   above), U12 [E][n][t], L21 [E][t][n], Ke [E][t][t]; perm [E][n] int32
+ *   (row i of P A is row perm[i] of A); w [E][n] and r [E][t] FP64.
+ * Outputs must not overlap inputs.  A zero or non-finite pivot latches
+ * IEDG_ERR_SINGULAR with the element index. */
+iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local,
+                          int32_t n_trace_elem, iedg_prec prec,
+                          const double* A, const double* B, const double* C,
+                          const double* D, const double* F,
+                          void* LU, int32_t* perm, void* U12, void* L21,
+                          double* w, void* Ke, double* r, hipStream_t stream);
+
+/* Right-hand-side-only condensation with retained factors (section 2.2.1):
+ * w = L^{-1} P F and r = -L21 w per element.  LU, L21 in `prec`
+ * storage as written by iedg_condense. */
+iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32_t n_local,
+                              int32_t n_trace_elem, iedg_prec prec,
+                              const void* LU, const int32_t* perm, const void* L21,
+                              const double* F, double* w, double* r,
+                              hipStream_t stream);
+
+/* ---- a2: assembly of K and R (section 2.2.1, eq. LS) ------------------ */
+/* Kbsr = sum_e P_e^T Ke_e P_e in the BSR layout of `mesh` (storage in
+ * `prec`, same element type as Ke), R = G + sum_e P_e^T r_e.  Sums over the
+ * (at most two) elements sharing a face are taken in ascending element
+ * order.  Ke/Kbsr may both be NULL (R only); r, G, R may all be NULL
+ * (K only). */
+iedg_status iedg_assemble(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
+                          const void* Ke, const double* r, const double* G,
+                          void* Kbsr, double* R, hipStream_t stream);
+
+/* ---- a3: BILU(0) (section 2.2.2) -------------------------------------- */
+/* Zero-fill block ILU of Kbsr in the mesh's row ordering.  Mbsr has the
+ * same layout: lower slots hold L~ (unit block-lower, identity diagonal
+ * implied), upper slots hold U~, diagonal slots hold the inverted pivot
+ * blocks U~_ii^{-1}.  Mbsr may equal Kbsr (in place).  A singular pivot
+ * block latches IEDG_ERR_SINGULAR with the block row. */
+iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
+                             const void* Kbsr, void* Mbsr, hipStream_t stream);
+
+/* ---- a4: GMRES (section 2.2.2, eq. LS1) ------------------------------- */
+typedef struct {
+  int32_t restart;      /* m, Krylov vectors per cycle (>= 1) */
+  int32_t max_iters;    /* cap on total Arnoldi steps */
+  double rtol;          /* accept when ||R - K x|| / ||R|| <= rtol */
+  double inner_factor;  /* inner stop: |g_{j+1}| <= inner_factor*rtol*||M^-1 R|| */
+  int32_t precond;      /* 1: M = BILU(0) factors in Mbsr; 0: M = I */
+} iedg_gmres_opts;
+
+typedef struct {
+  int32_t iters;        /* Arnoldi steps taken */
+  int32_t cycles;       /* restart cycles started */
+  int32_t converged;    /* 1 when the true residual met rtol */
+  double rel_resid;     /* final ||R - K x|| / ||R|| */
+} iedg_gmres_info;
+
+/* Solves M^{-1} K x = M^{-1} R from x0 = 0 (x is output only).  CGS
+ * applied twice per step; Givens rotations; every Krylov quantity FP64.
+ * K (and M) blocks in kprec (mprec) storage.  SYNCHRONISES the stream: it
+ * reads the residual estimate back after every step.  Returns
+ * IEDG_ERR_NOT_CONVERGED (with *info filled) when max_iters is reached. */
+iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,
+                             const void* Kbsr, iedg_prec mprec, const void* Mbsr,
+                             const double* R, double* x, const iedg_gmres_opts* opts,
+                             iedg_gmres_info* info, hipStream_t stream);
+
+/* y = K x (kprec blocks, FP64 vectors); exposed for testing and refinement. */
+iedg_status iedg_spmv(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,
+                      const void* Kbsr, const double* x, double* y, hipStream_t stream);
+/* y = M^{-1} x with BILU(0) factors (forward then backward block sweep). */
+iedg_status iedg_ilu0_apply(iedg_context ctx, iedg_mesh mesh, iedg_prec mprec,
+                            const void* Mbsr, const double* x, double* y,
+                            hipStream_t stream);
+
+/* ---- a5: local back-substitution (section 2.2.1) ---------------------- */
+/* z_e = U^{-1} (w_e - U12_e uhat_e) = A_e^{-1} (F_e - B_e uhat_e), where
+ * uhat_e gathers the element's t trace dofs from uhat [N_t].  LU, U12 in
+ * `prec` storage; w [E][n], uhat, z [E][n] FP64. */
+iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, int32_t n_local,
+                                 iedg_prec prec, const void* LU, const void* U12,
+                                 const double* w, const double* uhat, double* z,
+                                 hipStream_t stream);
+
+/* ---- a6: FP64 residual of the uncondensed system ---------------------- */
+/* rF_e = F_e - A_e z_e - B_e uhat_e,  rG = G - sum_e P_e^T (C_e z_e + D_e uhat_e),
+ * all FP64.  sums (device [4]) receives ||rF||^2, ||rG||^2, ||F||^2,
+ * ||G||^2 (deterministic two-stage reductions). */
+iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int32_t n_local,
+                               const double* A, const double* B, const double* C,
+                               const double* D, const double* F, const double* G,
+                               const double* z, const double* uhat,
+                               double* rF, double* rG, double* sums,
+                               hipStream_t stream);
+
+/* y += alpha * x over n FP64 values (refinement updates). */
+iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, const double* x,
+                      double* y, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IEDG_H */

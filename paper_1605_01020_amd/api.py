@@ -1,0 +1,219 @@
+"""Thin Python binding of libiedg: argument marshalling only.
+
+Every array is a torch tensor on the GPU (device memory and streams are the
+only things torch provides here); every step runs in the library's HIP
+kernels.  Functions enqueue on torch's current stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import F64, F32, BF16, GmresOpts, GmresInfo, MeshInfo
+
+PREC_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
+
+
+class IedgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("tensor must be on the GPU")
+            if not t.is_contiguous():
+                raise ValueError("tensor must be contiguous")
+
+
+class Context:
+    def __init__(self, device=None):
+        self.L = _lib.load()
+        dev = torch.cuda.current_device() if device is None else device
+        h = ctypes.c_void_p()
+        st = self.L.iedg_create(ctypes.byref(h), dev)
+        if st != 0:
+            raise IedgError(st, "iedg_create failed")
+        self.h = h
+
+    def check(self, st):
+        if st != 0:
+            raise IedgError(st, self.L.iedg_last_error(self.h).decode())
+
+    def sync_status(self):
+        """Synchronise and raise if a kernel latched a device-side error."""
+        idx = ctypes.c_int64(-1)
+        st = self.L.iedg_sync_status(self.h, _stream(), ctypes.byref(idx))
+        if st != 0:
+            err = IedgError(st, self.L.iedg_last_error(self.h).decode())
+            err.index = idx.value
+            raise err
+
+    def close(self):
+        if self.h:
+            self.L.iedg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """Trace topology + BSR pattern + BILU(0) schedule (iedg_mesh)."""
+
+    def __init__(self, ctx, elem_faces, n_face, face_dofs, ordering="colour", order=None):
+        self.ctx = ctx
+        ef = np.ascontiguousarray(elem_faces, dtype=np.int32)
+        code = {"colour": 0, "natural": 1, "given": 2}[ordering]
+        ordp = None
+        if order is not None:
+            order = np.ascontiguousarray(order, dtype=np.int32)
+            ordp = order.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.iedg_mesh_create(ctx.h, ef.shape[0], int(n_face), int(face_dofs),
+                                         ef.ctypes.data_as(ctypes.c_void_p), code, ordp,
+                                         ctypes.byref(h)))
+        self.h = h
+        info = MeshInfo()
+        ctx.check(ctx.L.iedg_mesh_query(h, ctypes.byref(info), None, None, None, None))
+        self.info = info
+        self.n_elem, self.n_face, self.b = info.n_elem, info.n_face, info.face_dofs
+        self.t = 6 * self.b
+        self.n_trace, self.nnzb, self.n_levels = info.n_trace, info.nnzb, info.n_levels
+
+    def query(self):
+        o = np.empty(self.n_face, np.int32)
+        lp = np.empty(self.n_levels + 1, np.int32)
+        rp = np.empty(self.n_face + 1, np.int32)
+        cf = np.empty(self.nnzb, np.int32)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self.ctx.check(self.ctx.L.iedg_mesh_query(self.h, None, ptr(o), ptr(lp), ptr(rp), ptr(cf)))
+        return {"order": o, "level_ptr": lp, "row_ptr": rp, "col_face": cf}
+
+    def close(self):
+        if self.h:
+            self.ctx.L.iedg_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def condense(ctx, A, B, C, D, F=None, prec=F64, out=None):
+    """a1: returns dict LU, perm, U12, L21, w, Ke, r (see iedg_condense)."""
+    _check_dev(A, B, C, D, F)
+    E, n, _ = A.shape
+    t = B.shape[2]
+    dt = PREC_DTYPE[prec]
+    o = out if out is not None else {}
+    dev = A.device
+    def need(key, shape, dtype):
+        if key not in o:
+            o[key] = torch.empty(shape, dtype=dtype, device=dev)
+        return o[key]
+    LU = need("LU", (E, n, n), dt)
+    perm = need("perm", (E, n), torch.int32)
+    U12 = need("U12", (E, n, t), dt)
+    L21 = need("L21", (E, t, n), dt)
+    Ke = need("Ke", (E, t, t), dt)
+    w = need("w", (E, n), torch.float64) if F is not None else None
+    r = need("r", (E, t), torch.float64) if F is not None else None
+    ctx.check(ctx.L.iedg_condense(ctx.h, E, n, t, prec, _p(A), _p(B), _p(C), _p(D), _p(F),
+                                  _p(LU), _p(perm), _p(U12), _p(L21), _p(w), _p(Ke), _p(r), _stream()))
+    return o
+
+
+def condense_rhs(ctx, fac, F, prec=F64, w=None, r=None):
+    LU, perm, L21 = fac["LU"], fac["perm"], fac["L21"]
+    E, n, _ = LU.shape
+    t = L21.shape[1]
+    w = torch.empty((E, n), dtype=torch.float64, device=F.device) if w is None else w
+    r = torch.empty((E, t), dtype=torch.float64, device=F.device) if r is None else r
+    ctx.check(ctx.L.iedg_condense_rhs(ctx.h, E, n, t, prec, _p(LU), _p(perm), _p(L21), _p(F),
+                                      _p(w), _p(r), _stream()))
+    return w, r
+
+
+def assemble(ctx, mesh, Ke=None, r=None, G=None, prec=F64, Kbsr=None, R=None):
+    if Ke is not None and Kbsr is None:
+        Kbsr = torch.empty((mesh.nnzb, mesh.b, mesh.b), dtype=PREC_DTYPE[prec], device=Ke.device)
+    dev = (Ke if Ke is not None else (r if r is not None else G)).device
+    if (r is not None or G is not None) and R is None:
+        R = torch.empty(mesh.n_trace, dtype=torch.float64, device=dev)
+    ctx.check(ctx.L.iedg_assemble(ctx.h, mesh.h, prec, _p(Ke), _p(r), _p(G), _p(Kbsr), _p(R), _stream()))
+    return Kbsr, R
+
+
+def factor_ilu0(ctx, mesh, Kbsr, prec=F64, Mbsr=None):
+    Mbsr = torch.empty_like(Kbsr) if Mbsr is None else Mbsr
+    ctx.check(ctx.L.iedg_factor_ilu0(ctx.h, mesh.h, prec, _p(Kbsr), _p(Mbsr), _stream()))
+    return Mbsr
+
+
+def gmres_solve(ctx, mesh, Kbsr, Mbsr, R, restart, rtol, max_iters=10000, inner_factor=0.1,
+                kprec=F64, mprec=F64, precond=True, x=None, raise_on_fail=True):
+    x = torch.empty_like(R) if x is None else x
+    opts = GmresOpts(restart, max_iters, rtol, inner_factor, 1 if precond else 0)
+    info = GmresInfo()
+    st = ctx.L.iedg_gmres_solve(ctx.h, mesh.h, kprec, _p(Kbsr), mprec, _p(Mbsr) if precond else None,
+                                _p(R), _p(x), ctypes.byref(opts), ctypes.byref(info), _stream())
+    res = {"iters": info.iters, "cycles": info.cycles, "converged": bool(info.converged),
+           "rel_resid": info.rel_resid, "status": st}
+    if st != 0 and (raise_on_fail or st != -3):
+        ctx.check(st)
+    return x, res
+
+
+def spmv(ctx, mesh, Kbsr, x, prec=F64, y=None):
+    y = torch.empty_like(x) if y is None else y
+    ctx.check(ctx.L.iedg_spmv(ctx.h, mesh.h, prec, _p(Kbsr), _p(x), _p(y), _stream()))
+    return y
+
+
+def ilu0_apply(ctx, mesh, Mbsr, x, prec=F64, y=None):
+    y = torch.empty_like(x) if y is None else y
+    ctx.check(ctx.L.iedg_ilu0_apply(ctx.h, mesh.h, prec, _p(Mbsr), _p(x), _p(y), _stream()))
+    return y
+
+
+def backsolve_local(ctx, mesh, fac, uhat, prec=F64, w=None, z=None):
+    LU, U12 = fac["LU"], fac["U12"]
+    w = fac["w"] if w is None else w
+    E, n, _ = LU.shape
+    z = torch.empty((E, n), dtype=torch.float64, device=uhat.device) if z is None else z
+    ctx.check(ctx.L.iedg_backsolve_local(ctx.h, mesh.h, n, prec, _p(LU), _p(U12), _p(w), _p(uhat),
+                                         _p(z), _stream()))
+    return z
+
+
+def residual_full(ctx, mesh, A, B, C, D, F, G, z, uhat, rF=None, rG=None, sums=None):
+    E, n, _ = A.shape
+    rF = torch.empty((E, n), dtype=torch.float64, device=A.device) if rF is None else rF
+    rG = torch.empty_like(G) if rG is None else rG
+    sums = torch.empty(4, dtype=torch.float64, device=A.device) if sums is None else sums
+    ctx.check(ctx.L.iedg_residual_full(ctx.h, mesh.h, n, _p(A), _p(B), _p(C), _p(D), _p(F), _p(G),
+                                       _p(z), _p(uhat), _p(rF), _p(rG), _p(sums), _stream()))
+    return rF, rG, sums
+
+
+def axpy(ctx, alpha, x, y):
+    ctx.check(ctx.L.iedg_axpy(ctx.h, x.numel(), float(alpha), _p(x), _p(y), _stream()))
+    return y

@@ -1,0 +1,111 @@
+// Internal helpers shared by the gfx950 kernels of libiedg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "iedg.h"
+
+namespace iedg {
+
+constexpr int kWave = 64;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Lane layouts of the 16x16x4 MFMA operations on gfx950 (measured on the
+// device).  A operand: lane l holds A[l % 16][l / 16]; B operand: lane l
+// holds B[l / 16][l % 16].  Accumulator element v of lane l sits at
+// column l % 16 and row
+//   FP64 (v_mfma_f64_16x16x4f64): l / 16 + 4 v
+//   FP32 (v_mfma_f32_16x16x4f32): 4 (l / 16) + v
+template <typename T> struct Mfma;
+
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static inline acc_t mac(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static inline acc_t mac(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Wave-wide sum (64 lanes) with a fixed butterfly order: deterministic.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block-wide deterministic sum; `red` is LDS of at least blockDim/64 doubles.
+// Every thread receives the result.
+__device__ inline double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// Device status word: first failing index (element or block row) + code.
+struct DeviceStatus {
+  int32_t code;   // 0 = ok, otherwise an iedg_status value
+  int32_t pad;
+  int64_t index;  // smallest failing index seen
+};
+
+__device__ inline void latch_status(DeviceStatus* st, int32_t code, int64_t index) {
+  // keep the smallest index: deterministic regardless of scheduling
+  atomicMin(reinterpret_cast<unsigned long long*>(&st->index),
+            static_cast<unsigned long long>(index));
+  atomicExch(&st->code, code);
+}
+
+}  // namespace iedg
+
+// ---- host-side context --------------------------------------------------
+struct iedg_context_s {
+  int device = 0;
+  std::string last_error;
+  iedg::DeviceStatus* d_status = nullptr;   // device
+  iedg::DeviceStatus* h_status = nullptr;   // pinned host mirror
+  double* h_scalars = nullptr;              // pinned host readback area
+  // GMRES / reduction workspace, grown on demand
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+
+namespace iedg {
+
+iedg_status set_error(iedg_context ctx, iedg_status s, const char* fmt, ...);
+iedg_status hip_check(iedg_context ctx, hipError_t e, const char* what);
+iedg_status ensure_work(iedg_context ctx, size_t bytes);
+
+}  // namespace iedg
+
+#define IEDG_HIP(ctx, call)                                              \
+  do {                                                                   \
+    hipError_t _e = (call);                                              \
+    if (_e != hipSuccess) return iedg::hip_check((ctx), _e, #call);      \
+  } while (0)
+
+#define IEDG_LAUNCH_CHECK(ctx, what)                                     \
+  do {                                                                   \
+    hipError_t _e = hipGetLastError();                                   \
+    if (_e != hipSuccess) return iedg::hip_check((ctx), _e, what);       \
+  } while (0)

@@ -1,0 +1,323 @@
+// Context, error handling, mesh construction (host code of libiedg).
+#include <algorithm>
+#include <cstdarg>
+#include <climits>
+#include <set>
+
+#include "common.h"
+#include "mesh.h"
+
+namespace iedg {
+
+iedg_status set_error(iedg_context ctx, iedg_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    ctx->last_error = buf;
+  }
+  return s;
+}
+
+iedg_status hip_check(iedg_context ctx, hipError_t e, const char* what) {
+  return set_error(ctx, IEDG_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+iedg_status ensure_work(iedg_context ctx, size_t bytes) {
+  if (bytes <= ctx->work_bytes) return IEDG_OK;
+  if (ctx->work) {
+    hipDeviceSynchronize();
+    hipFree(ctx->work);
+    ctx->work = nullptr;
+    ctx->work_bytes = 0;
+  }
+  bytes = (bytes + 4095) & ~size_t(4095);
+  hipError_t e = hipMalloc(&ctx->work, bytes);
+  if (e != hipSuccess) return set_error(ctx, IEDG_ERR_OOM, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+  ctx->work_bytes = bytes;
+  return IEDG_OK;
+}
+
+template <typename T>
+static iedg_status upload(iedg_context ctx, T** dst, const std::vector<T>& src) {
+  size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
+  IEDG_HIP(ctx, hipMalloc(reinterpret_cast<void**>(dst), bytes));
+  if (!src.empty()) IEDG_HIP(ctx, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return IEDG_OK;
+}
+
+}  // namespace iedg
+
+using namespace iedg;
+
+extern "C" {
+
+const char* iedg_status_string(iedg_status s) {
+  switch (s) {
+    case IEDG_OK: return "ok";
+    case IEDG_ERR_INVALID_ARG: return "invalid argument";
+    case IEDG_ERR_SINGULAR: return "singular pivot";
+    case IEDG_ERR_NOT_CONVERGED: return "not converged";
+    case IEDG_ERR_NONFINITE: return "non-finite value";
+    case IEDG_ERR_OOM: return "out of device memory";
+    case IEDG_ERR_HIP: return "HIP runtime error";
+    case IEDG_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+iedg_status iedg_create(iedg_context* out, int device) {
+  if (!out) return IEDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  auto* ctx = new iedg_context_s();
+  ctx->device = device;
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_status, sizeof(DeviceStatus));
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->h_status, sizeof(DeviceStatus), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&ctx->h_scalars, 4096, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    DeviceStatus init{0, 0, INT64_MAX};
+    e = hipMemcpy(ctx->d_status, &init, sizeof(init), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    iedg_destroy(ctx);
+    return IEDG_ERR_HIP;
+  }
+  *out = ctx;
+  return IEDG_OK;
+}
+
+void iedg_destroy(iedg_context ctx) {
+  if (!ctx) return;
+  hipDeviceSynchronize();
+  if (ctx->d_status) hipFree(ctx->d_status);
+  if (ctx->h_status) hipHostFree(ctx->h_status);
+  if (ctx->h_scalars) hipHostFree(ctx->h_scalars);
+  if (ctx->work) hipFree(ctx->work);
+  delete ctx;
+}
+
+const char* iedg_last_error(iedg_context ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+iedg_status iedg_sync_status(iedg_context ctx, hipStream_t stream, int64_t* bad_index) {
+  if (!ctx) return IEDG_ERR_INVALID_ARG;
+  IEDG_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(DeviceStatus), hipMemcpyDeviceToHost, stream));
+  IEDG_HIP(ctx, hipStreamSynchronize(stream));
+  DeviceStatus st = *ctx->h_status;
+  if (bad_index) *bad_index = st.code ? st.index : -1;
+  if (st.code) {
+    DeviceStatus init{0, 0, INT64_MAX};
+    IEDG_HIP(ctx, hipMemcpy(ctx->d_status, &init, sizeof(init), hipMemcpyHostToDevice));
+    return set_error(ctx, static_cast<iedg_status>(st.code), "device reported %s at index %lld",
+                     iedg_status_string(static_cast<iedg_status>(st.code)), (long long)st.index);
+  }
+  return IEDG_OK;
+}
+
+iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, int32_t face_dofs,
+                             const int32_t* elem_faces, int32_t ordering, const int32_t* order_in,
+                             iedg_mesh* out) {
+  if (!ctx || !out || !elem_faces || n_elem <= 0 || n_face <= 0 || face_dofs <= 0)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: bad arguments");
+  if (face_dofs > 128)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "mesh_create: face_dofs %d > 128", face_dofs);
+  *out = nullptr;
+  const int E = n_elem, NF = n_face;
+  // element incidence and validity
+  std::vector<std::vector<std::pair<int, int>>> face_elems(NF);
+  for (int e = 0; e < E; ++e)
+    for (int a = 0; a < 6; ++a) {
+      int f = elem_faces[6 * e + a];
+      if (f < 0 || f >= NF) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face id %d out of range", f);
+      for (int a2 = 0; a2 < a; ++a2)
+        if (elem_faces[6 * e + a2] == f)
+          return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: element %d lists face %d twice", e, f);
+      face_elems[f].push_back({e, a});
+    }
+  for (int f = 0; f < NF; ++f) {
+    if (face_elems[f].empty()) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face %d has no element", f);
+    if (face_elems[f].size() > 2)
+      return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face %d shared by %zu elements", f, face_elems[f].size());
+  }
+  // coupled faces (pattern), sorted by face id
+  std::vector<std::vector<int>> adj(NF);
+  for (int f = 0; f < NF; ++f) {
+    std::set<int> s;
+    for (auto& ea : face_elems[f])
+      for (int a = 0; a < 6; ++a) s.insert(elem_faces[6 * ea.first + a]);
+    adj[f].assign(s.begin(), s.end());
+  }
+  auto* m = new iedg_mesh_s();
+  m->ctx = ctx;
+  m->n_elem = E;
+  m->n_face = NF;
+  m->b = face_dofs;
+  m->t = 6 * face_dofs;
+  m->n_trace = int64_t(NF) * face_dofs;
+  // ordering
+  m->order.resize(NF);
+  if (ordering == 1) {
+    for (int f = 0; f < NF; ++f) m->order[f] = f;
+  } else if (ordering == 2) {
+    if (!order_in) { delete m; return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: ordering 2 needs order"); }
+    std::vector<char> seen(NF, 0);
+    for (int i = 0; i < NF; ++i) {
+      int f = order_in[i];
+      if (f < 0 || f >= NF || seen[f]) { delete m; return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: order is not a permutation"); }
+      seen[f] = 1;
+      m->order[i] = f;
+    }
+  } else if (ordering == 0) {
+    // greedy colouring: ascending face id, smallest colour not used by an
+    // already coloured coupled face; rows listed by (colour, face id)
+    std::vector<int> colour(NF, -1);
+    int ncol = 0;
+    for (int f = 0; f < NF; ++f) {
+      std::vector<char> used(adj[f].size() + 1, 0);
+      for (int g : adj[f])
+        if (g != f && colour[g] >= 0 && colour[g] < (int)used.size()) used[colour[g]] = 1;
+      int c = 0;
+      while (used[c]) ++c;
+      colour[f] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+    int i = 0;
+    for (int c = 0; c < ncol; ++c)
+      for (int f = 0; f < NF; ++f)
+        if (colour[f] == c) m->order[i++] = f;
+  } else {
+    delete m;
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: unknown ordering %d", ordering);
+  }
+  m->pos.resize(NF);
+  for (int i = 0; i < NF; ++i) m->pos[m->order[i]] = i;
+  // BSR pattern in position order
+  m->row_ptr.assign(NF + 1, 0);
+  std::vector<int32_t> diag_slot(NF);
+  for (int i = 0; i < NF; ++i) {
+    int f = m->order[i];
+    std::vector<int> cols = adj[f];
+    std::sort(cols.begin(), cols.end(), [&](int x, int y) { return m->pos[x] < m->pos[y]; });
+    m->row_ptr[i + 1] = m->row_ptr[i] + (int)cols.size();
+    for (int g : cols) {
+      if (g == f) diag_slot[i] = (int32_t)m->col_face.size();
+      m->col_face.push_back(g);
+    }
+  }
+  m->nnzb = (int64_t)m->col_face.size();
+  auto slot_of = [&](int i, int g) -> int {
+    for (int s = m->row_ptr[i]; s < m->row_ptr[i + 1]; ++s)
+      if (m->col_face[s] == g) return s;
+    return -1;
+  };
+  // assembly gather map: block (f, g) receives Ke_e[a][c] for every element e
+  // holding f at local face a and g at local face c (ascending e)
+  std::vector<int32_t> asm_src(2 * m->nnzb, -1);
+  for (int i = 0; i < NF; ++i) {
+    int f = m->order[i];
+    for (int s = m->row_ptr[i]; s < m->row_ptr[i + 1]; ++s) {
+      int g = m->col_face[s], k = 0;
+      for (auto& ea : face_elems[f]) {
+        int e = ea.first;
+        for (int c = 0; c < 6; ++c)
+          if (elem_faces[6 * e + c] == g) asm_src[2 * s + (k++)] = e * 36 + ea.second * 6 + c;
+      }
+    }
+  }
+  std::vector<int32_t> face_src(2 * NF, -1);
+  for (int f = 0; f < NF; ++f)
+    for (size_t k = 0; k < face_elems[f].size(); ++k)
+      face_src[2 * f + k] = face_elems[f][k].first * 6 + face_elems[f][k].second;
+  // level sets of the lower-triangular dependency graph
+  std::vector<int> level(NF, 0);
+  int nlev = 0;
+  for (int i = 0; i < NF; ++i) {
+    int lv = 0;
+    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) lv = std::max(lv, level[m->pos[m->col_face[s]]] + 1);
+    level[i] = lv;
+    nlev = std::max(nlev, lv + 1);
+  }
+  m->n_levels = nlev;
+  m->level_ptr.assign(nlev + 1, 0);
+  for (int i = 0; i < NF; ++i) m->level_ptr[level[i] + 1]++;
+  for (int l = 0; l < nlev; ++l) m->level_ptr[l + 1] += m->level_ptr[l];
+  m->level_rows.resize(NF);
+  {
+    std::vector<int> fill(m->level_ptr.begin(), m->level_ptr.end() - 1);
+    for (int i = 0; i < NF; ++i) m->level_rows[fill[level[i]]++] = i;
+  }
+  // BILU(0) schedule: for row i, lower slots (i,k) in elimination order; for
+  // each, the updates A_ij -= L_ik U_kj over j later than k coupled to both
+  std::vector<int32_t> lptr(NF + 1, 0), lslots, uptr(1, 0), upd;
+  for (int i = 0; i < NF; ++i) {
+    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) {
+      int k = m->pos[m->col_face[s]];
+      lslots.push_back(s);
+      lslots.push_back(diag_slot[k]);
+      for (int s2 = diag_slot[k] + 1; s2 < m->row_ptr[k + 1]; ++s2) {
+        int j = m->col_face[s2];
+        int sij = slot_of(i, j);
+        if (sij >= 0) {
+          upd.push_back(s2);
+          upd.push_back(sij);
+        }
+      }
+      uptr.push_back((int32_t)(upd.size() / 2));
+    }
+    lptr[i + 1] = (int32_t)(lslots.size() / 2);
+  }
+  m->n_lslots = (int64_t)lslots.size() / 2;
+  m->n_updates = (int64_t)upd.size() / 2;
+  std::vector<int32_t> ef(elem_faces, elem_faces + 6 * (size_t)E);
+  iedg_status st = IEDG_OK;
+  if (st == IEDG_OK) st = upload(ctx, &m->d_elem_faces, ef);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_row_face, m->order);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_row_ptr, m->row_ptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_col_face, m->col_face);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_diag_slot, diag_slot);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_level_rows, m->level_rows);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_asm_src, asm_src);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_face_src, face_src);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_lptr, lptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_l, lslots);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_uptr, uptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_upd, upd);
+  if (st != IEDG_OK) {
+    iedg_mesh_destroy(m);
+    return st;
+  }
+  *out = m;
+  return IEDG_OK;
+}
+
+void iedg_mesh_destroy(iedg_mesh m) {
+  if (!m) return;
+  int32_t* ptrs[] = {m->d_elem_faces, m->d_row_face, m->d_row_ptr, m->d_col_face,
+                     m->d_diag_slot, m->d_level_rows, m->d_asm_src, m->d_face_src,
+                     m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd};
+  for (int32_t* p : ptrs)
+    if (p) hipFree(p);
+  delete m;
+}
+
+iedg_status iedg_mesh_query(iedg_mesh m, iedg_mesh_info* info, int32_t* order, int32_t* level_ptr,
+                            int32_t* row_ptr, int32_t* col_face) {
+  if (!m) return IEDG_ERR_INVALID_ARG;
+  if (info) {
+    info->n_elem = m->n_elem;
+    info->n_face = m->n_face;
+    info->face_dofs = m->b;
+    info->n_trace = m->n_trace;
+    info->nnzb = m->nnzb;
+    info->n_levels = m->n_levels;
+  }
+  if (order) std::copy(m->order.begin(), m->order.end(), order);
+  if (level_ptr) std::copy(m->level_ptr.begin(), m->level_ptr.end(), level_ptr);
+  if (row_ptr) std::copy(m->row_ptr.begin(), m->row_ptr.end(), row_ptr);
+  if (col_face) std::copy(m->col_face.begin(), m->col_face.end(), col_face);
+  return IEDG_OK;
+}
+
+}  // extern "C"

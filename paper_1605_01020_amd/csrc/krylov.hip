@@ -1,0 +1,350 @@
+// Restarted GMRES(m), left preconditioned by BILU(0), with classical
+// Gram-Schmidt applied twice per Arnoldi step (section 2.2.2, eq. LS1;
+// Saad and Schultz 1986).  Every Krylov quantity is FP64.  Reductions are
+// two-stage with a fixed chunk-to-workgroup map, so results are bitwise
+// reproducible.
+#include <cmath>
+
+#include "common.h"
+#include "mesh.h"
+
+namespace iedg {
+
+iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x,
+                        const double* rhs, double* y, int mode, hipStream_t stream);
+iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
+                              double* y, hipStream_t stream);
+
+constexpr int KTHR = 256;
+constexpr int KPER = 8;                 // values per thread per chunk
+constexpr int KCH = KTHR * KPER;        // chunk length per workgroup
+constexpr int MAXV = 256;               // max Krylov vectors per cycle + 2
+
+// partial[c * ld + k] = sum over chunk c of V_k . w   (k < nv), and, when
+// self >= 0, partial[c * ld + self] = w . w
+__global__ __launch_bounds__(KTHR) void dots_kernel(const double* V, int64_t ldv, int nv, const double* w,
+                                                    int64_t N, double* partial, int ld, int self) {
+  __shared__ double red[KTHR / 64];
+  const int c = blockIdx.x;
+  const int64_t base = (int64_t)c * KCH;
+  double wv[KPER];
+#pragma unroll
+  for (int q = 0; q < KPER; ++q) {
+    const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+    wv[q] = i < N ? w[i] : 0.0;
+  }
+  for (int k = 0; k < nv; ++k) {
+    const double* v = V + (int64_t)k * ldv;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) {
+      const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+      if (i < N) s += v[i] * wv[q];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[(int64_t)c * ld + k] = s;
+  }
+  if (self >= 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) s += wv[q] * wv[q];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial[(int64_t)c * ld + self] = s;
+  }
+}
+
+// Each workgroup reduces partial_in (nb chunks, fixed order) to h[0:nv],
+// then w[chunk] -= sum_k h_k V_k[chunk].  Workgroup 0 stores h into
+// hcol (accumulate = 0: overwrite, 1: add).  Afterwards, when next_dots,
+// partial_out[c][k] = V_k . w over the chunk (k < nv); otherwise
+// partial_out[c][0] = w . w over the chunk.
+__global__ __launch_bounds__(KTHR) void cgs_update_kernel(const double* V, int64_t ldv, int nv, double* w,
+                                                          int64_t N, const double* partial_in, int nb, int ld_in,
+                                                          double* hcol, int accumulate, double* partial_out,
+                                                          int ld_out, int next_dots) {
+  __shared__ double h[MAXV];
+  __shared__ double red[KTHR / 64];
+  const int c = blockIdx.x;
+  for (int k = threadIdx.x; k < nv; k += KTHR) {
+    double s = 0.0;
+    for (int q = 0; q < nb; ++q) s += partial_in[(int64_t)q * ld_in + k];
+    h[k] = s;
+  }
+  __syncthreads();
+  if (c == 0)
+    for (int k = threadIdx.x; k < nv; k += KTHR) hcol[k] = accumulate ? hcol[k] + h[k] : h[k];
+  const int64_t base = (int64_t)c * KCH;
+  double wv[KPER];
+#pragma unroll
+  for (int q = 0; q < KPER; ++q) {
+    const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+    wv[q] = i < N ? w[i] : 0.0;
+  }
+  for (int k = 0; k < nv; ++k) {
+    const double* v = V + (int64_t)k * ldv;
+    const double hk = h[k];
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) {
+      const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+      if (i < N) wv[q] -= hk * v[i];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KPER; ++q) {
+    const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+    if (i < N) w[i] = wv[q];
+  }
+  if (next_dots) {
+    for (int k = 0; k < nv; ++k) {
+      const double* v = V + (int64_t)k * ldv;
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < KPER; ++q) {
+        const int64_t i = base + threadIdx.x + (int64_t)q * KTHR;
+        if (i < N) s += v[i] * wv[q];
+      }
+      s = block_sum(s, red);
+      if (threadIdx.x == 0) partial_out[(int64_t)c * ld_out + k] = s;
+    }
+  } else {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < KPER; ++q) s += wv[q] * wv[q];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) partial_out[(int64_t)c * ld_out] = s;
+  }
+}
+
+// Scalars shared between the Arnoldi kernels and the host readback.
+struct GmresScal {
+  double est;       // |g_{j+1}|
+  double hn;        // ||w|| after orthogonalisation
+  double wn0;       // ||w|| before orthogonalisation
+  double inv_scale; // 1 / value used by scale_kernel
+  double norm;      // a norm requested by the host
+  double pad[3];
+};
+
+// Reduce nb partial sums -> sqrt, fixed order (one thread).
+__device__ inline double reduce_sqrt(const double* partial, int nb, int ld, int idx) {
+  double s = 0.0;
+  for (int q = 0; q < nb; ++q) s += partial[(int64_t)q * ld + idx];
+  return sqrt(s);
+}
+
+// Finish Arnoldi step j: H[j+1, j] = ||w||, apply the stored rotations to
+// column j, form the new rotation and update g.  One thread.
+__global__ void arnoldi_finish_kernel(const double* partial_norm, int nb, const double* partial_w0, int ld_w0,
+                                      int idx_w0, double* H, int ldh, int j, double* cs, double* sn, double* g,
+                                      GmresScal* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double hn = reduce_sqrt(partial_norm, nb, 1, 0);
+  const double wn0 = reduce_sqrt(partial_w0, nb, ld_w0, idx_w0);
+  double* hc = H + (int64_t)j * ldh;
+  hc[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a = hc[i], b = hc[i + 1];
+    hc[i] = cs[i] * a + sn[i] * b;
+    hc[i + 1] = -sn[i] * a + cs[i] * b;
+  }
+  const double a = hc[j], b = hc[j + 1];
+  double c = 1.0, s = 0.0, r = a;
+  if (b != 0.0) {
+    r = hypot(a, b);
+    c = a / r;
+    s = b / r;
+  }
+  cs[j] = c;
+  sn[j] = s;
+  hc[j] = r;
+  hc[j + 1] = 0.0;
+  const double gj = g[j];
+  g[j + 1] = -s * gj;
+  g[j] = c * gj;
+  sc->est = fabs(g[j + 1]);
+  sc->hn = hn;
+  sc->wn0 = wn0;
+  sc->inv_scale = hn > 0.0 ? 1.0 / hn : 0.0;
+}
+
+// sc->norm = sqrt(sum of partials); sc->inv_scale = 1 / norm; optionally g = (norm, 0, ...)
+__global__ void norm_finish_kernel(const double* partial, int nb, int ld, int idx, GmresScal* sc, double* g,
+                                   int m1) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nrm = reduce_sqrt(partial, nb, ld, idx);
+  sc->norm = nrm;
+  sc->inv_scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  if (g) {
+    g[0] = nrm;
+    for (int i = 1; i < m1; ++i) g[i] = 0.0;
+  }
+}
+
+__global__ void scale_kernel(double* v, int64_t N, const GmresScal* sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] *= sc->inv_scale;
+}
+
+__global__ void fill_kernel(double* v, int64_t N, double val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) v[i] = val;
+}
+
+__global__ void copy_kernel(double* dst, const double* src, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[i];
+}
+
+// Back substitution H(0:k, 0:k) y = g(0:k), upper triangular.  One thread.
+__global__ void hsolve_kernel(const double* H, int ldh, const double* g, int k, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[(int64_t)j * ldh + i] * y[j];
+    y[i] = s / H[(int64_t)i * ldh + i];
+  }
+}
+
+// x += sum_{k < nv} y_k V_k
+__global__ void multi_axpy_kernel(double* x, const double* V, int64_t ldv, int nv, const double* y, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double s = x[i];
+  for (int k = 0; k < nv; ++k) s += y[k] * V[(int64_t)k * ldv + i];
+  x[i] = s;
+}
+
+__global__ void axpy_kernel(int64_t n, double alpha, const double* x, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += alpha * x[i];
+}
+
+static inline unsigned grid1(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace iedg
+
+using namespace iedg;
+
+extern "C" iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, const double* x, double* y,
+                                 hipStream_t stream) {
+  if (!ctx || n < 0 || (n > 0 && (!x || !y))) return IEDG_ERR_INVALID_ARG;
+  if (n == 0) return IEDG_OK;
+  hipLaunchKernelGGL(axpy_kernel, dim3(grid1(n)), dim3(256), 0, stream, n, alpha, x, y);
+  IEDG_LAUNCH_CHECK(ctx, "axpy launch");
+  return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec, const void* Kbsr,
+                                        iedg_prec mprec, const void* Mbsr, const double* R, double* x,
+                                        const iedg_gmres_opts* opts, iedg_gmres_info* info, hipStream_t stream) {
+  if (!ctx || !mesh || !Kbsr || !R || !x || !opts) return IEDG_ERR_INVALID_ARG;
+  const int m = opts->restart;
+  if (m < 1 || m > MAXV - 2) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: restart %d outside [1, %d]", m, MAXV - 2);
+  if (opts->precond && !Mbsr) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: precond without factors");
+  if (!(opts->rtol > 0.0)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: rtol must be > 0");
+  const int64_t N = mesh->n_trace;
+  const int nb = (int)((N + KCH - 1) / KCH);
+  const int ldp = m + 2;
+  // workspace layout (doubles)
+  const int64_t ldv = (N + 63) & ~int64_t(63);
+  size_t off = 0;
+  auto take = [&](size_t count) { size_t o = off; off += (count + 63) & ~size_t(63); return o; };
+  const size_t oV = take((size_t)(m + 1) * ldv), oT = take(ldv), oP1 = take((size_t)nb * ldp),
+               oP2 = take((size_t)nb * ldp), oP3 = take((size_t)nb), oH = take((size_t)(m + 1) * m),
+               oCS = take(m), oSN = take(m), oG = take(m + 1), oY = take(m), oSC = take(sizeof(GmresScal) / 8);
+  iedg_status st = ensure_work(ctx, off * sizeof(double));
+  if (st != IEDG_OK) return st;
+  double* W = static_cast<double*>(ctx->work);
+  double *V = W + oV, *tmp = W + oT, *P1 = W + oP1, *P2 = W + oP2, *P3 = W + oP3, *H = W + oH, *CS = W + oCS,
+         *SN = W + oSN, *G = W + oG, *Y = W + oY;
+  GmresScal* SC = reinterpret_cast<GmresScal*>(W + oSC);
+  GmresScal* hsc = reinterpret_cast<GmresScal*>(ctx->h_scalars);
+  auto readback = [&]() -> iedg_status {
+    IEDG_HIP(ctx, hipMemcpyAsync(hsc, SC, sizeof(GmresScal), hipMemcpyDeviceToHost, stream));
+    IEDG_HIP(ctx, hipStreamSynchronize(stream));
+    return IEDG_OK;
+  };
+  auto precond = [&](const double* in, double* out) -> iedg_status {
+    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream);
+    hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, out, in, N);
+    return IEDG_OK;
+  };
+  // norm of a vector into SC->norm (and SC->inv_scale); optional g init
+  auto vnorm = [&](const double* v, double* ginit) -> iedg_status {
+    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, v, ldv, 0, v, N, P3, 1, 0);
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, ginit, m + 1);
+    return readback();
+  };
+  iedg_gmres_info inf{0, 0, 0, 0.0};
+  // ||R||
+  if ((st = vnorm(R, nullptr)) != IEDG_OK) return st;
+  const double nR = hsc->norm;
+  if (!std::isfinite(nR)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: right-hand side is not finite");
+  hipLaunchKernelGGL(fill_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, N, 0.0);
+  if (nR == 0.0) {
+    inf.converged = 1;
+    if (info) *info = inf;
+    return IEDG_OK;
+  }
+  // ||M^{-1} R|| sets the inner tolerance
+  if ((st = precond(R, tmp)) != IEDG_OK) return st;
+  if ((st = vnorm(tmp, nullptr)) != IEDG_OK) return st;
+  const double inner_tol = opts->inner_factor * opts->rtol * hsc->norm;
+  double rho = 1.0;
+  bool first = true;
+  while (true) {
+    // true residual r = R - K x (x = 0 on the first cycle)
+    if (first) {
+      hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, tmp, R, N);
+    } else {
+      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream)) != IEDG_OK) return st;
+    }
+    if ((st = vnorm(tmp, nullptr)) != IEDG_OK) return st;
+    rho = hsc->norm / nR;
+    first = false;
+    if (!std::isfinite(rho)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: residual is not finite");
+    if (rho <= opts->rtol) { inf.converged = 1; break; }
+    if (inf.iters >= opts->max_iters) break;
+    inf.cycles++;
+    // v0 = M^{-1} r / ||M^{-1} r||,  g = (beta, 0, ...)
+    if ((st = precond(tmp, V)) != IEDG_OK) return st;
+    if ((st = vnorm(V, G)) != IEDG_OK) return st;
+    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, N, SC);
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + (int64_t)j * ldv;
+      double* w = V + (int64_t)(j + 1) * ldv;
+      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream)) != IEDG_OK) return st;
+      if ((st = precond(tmp, w)) != IEDG_OK) return st;
+      const int nv = j + 1;
+      double* hcol = H + (int64_t)j * (m + 1);
+      // pass 1 dots (+ ||w||^2 before orthogonalisation at index nv)
+      hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv);
+      // pass 1 update + pass 2 dots
+      hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, nb, ldp, hcol, 0,
+                         P2, ldp, 1);
+      // pass 2 update + ||w||^2
+      hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P2, nb, ldp, hcol, 1,
+                         P3, 1, 0);
+      hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, P1, ldp, nv, H, m + 1, j, CS,
+                         SN, G, SC);
+      hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, SC);
+      IEDG_LAUNCH_CHECK(ctx, "arnoldi launch");
+      if ((st = readback()) != IEDG_OK) return st;
+      inf.iters++;
+      k = j + 1;
+      const bool breakdown = hsc->hn <= 1e-14 * hsc->wn0;
+      if (!std::isfinite(hsc->est)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: Arnoldi produced non-finite values");
+      if (hsc->est <= inner_tol || breakdown || inf.iters >= opts->max_iters) break;
+    }
+    hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, H, m + 1, G, k, Y);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, k, Y, N);
+    IEDG_LAUNCH_CHECK(ctx, "gmres update launch");
+  }
+  inf.rel_resid = rho;
+  if (info) *info = inf;
+  if (!inf.converged)
+    return set_error(ctx, IEDG_ERR_NOT_CONVERGED, "gmres: %d iterations, relative residual %.3e > %.3e", inf.iters, rho,
+                     opts->rtol);
+  return IEDG_OK;
+}

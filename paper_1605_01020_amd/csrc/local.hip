@@ -1,0 +1,214 @@
+// Element-local kernels on gfx950: recovery of the element unknowns
+// (section 2.2.1) and the FP64 residual of the uncondensed Newton system.
+#include "common.h"
+#include "mesh.h"
+
+namespace iedg {
+
+constexpr int LTHR = 256;
+constexpr int LWAVES = LTHR / 64;
+
+// z_e = U^{-1} (w_e - U12_e uhat_e): one workgroup per element.
+template <typename T>
+__global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, const int32_t* elem_faces, const T* LU,
+                                                         const T* U12, const double* w, const double* uhat,
+                                                         double* z) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* ue = reinterpret_cast<double*>(smem_raw);  // t
+  double* y = ue + t;                                // n
+  double* blk = y + n;                               // 64 x 65
+  const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < t; i += LTHR) {
+    const int a = i / b, l = i % b;
+    ue[i] = uhat[(size_t)elem_faces[6 * e + a] * b + l];
+  }
+  __syncthreads();
+  const T* U12e = U12 + (size_t)e * n * t;
+  for (int i = wv; i < n; i += LWAVES) {
+    const T* row = U12e + (size_t)i * t;
+    double s = 0.0;
+    for (int k = lane; k < t; k += 64) s += (double)row[k] * ue[k];
+    s = wave_sum(s);
+    if (lane == 0) y[i] = w[(size_t)e * n + i] - s;
+  }
+  __syncthreads();
+  const T* U = LU + (size_t)e * n * n;
+  const int nblk = (n + 63) / 64;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int i0 = bi * 64, i1 = min(i0 + 64, n), bw = i1 - i0;
+    // y[i0:i1] -= U[i0:i1, i1:n] z[i1:n]   (z stored in y beyond i1)
+    for (int i = i0 + wv; i < i1; i += LWAVES) {
+      const T* row = U + (size_t)i * n;
+      double s = 0.0;
+      for (int k = i1 + lane; k < n; k += 64) s += (double)row[k] * y[k];
+      s = wave_sum(s);
+      if (lane == 0) y[i] -= s;
+    }
+    for (int q = tid; q < 64 * 64; q += LTHR) {
+      const int rr = q / 64, cc = q % 64;
+      blk[rr * 65 + cc] = (rr < bw && cc < bw && cc >= rr) ? (double)U[(size_t)(i0 + rr) * n + i0 + cc] : 0.0;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      double yl = lane < bw ? y[i0 + lane] : 0.0;
+      for (int k = bw - 1; k >= 0; --k) {
+        const double zk = __shfl(yl, k, kWave) / blk[k * 65 + k];
+        if (lane == k) yl = zk;
+        if (lane < k) yl -= blk[lane * 65 + k] * zk;
+      }
+      if (lane < bw) y[i0 + lane] = yl;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += LTHR) z[(size_t)e * n + i] = y[i];
+}
+
+// Per element: rF_e = F_e - A_e z_e - B_e u_e; q_e = C_e z_e + D_e u_e; also
+// per-element sums of rF^2 and F^2 (fixed-order block reduction).
+__global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b, const int32_t* elem_faces,
+                                                             const double* A, const double* B, const double* C,
+                                                             const double* D, const double* F, const double* z,
+                                                             const double* uhat, double* rF, double* q,
+                                                             double* part_rf, double* part_f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* ue = reinterpret_cast<double*>(smem_raw);  // t
+  double* ze = ue + t;                               // n
+  double* red = ze + n;                              // LWAVES
+  double* acc = red + LWAVES;                        // 2 * LWAVES
+  const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < t; i += LTHR) {
+    const int a = i / b, l = i % b;
+    ue[i] = uhat[(size_t)elem_faces[6 * e + a] * b + l];
+  }
+  for (int i = tid; i < n; i += LTHR) ze[i] = z[(size_t)e * n + i];
+  __syncthreads();
+  const size_t nn = (size_t)n * n, nt = (size_t)n * t, tt = (size_t)t * t;
+  const double *Ae = A + e * nn, *Be = B + e * nt, *Ce = C + e * nt, *De = D + e * tt;
+  double srf = 0.0, sf = 0.0;  // per-wave partials (lane 0)
+  for (int i = wv; i < n; i += LWAVES) {
+    const double* ra = Ae + (size_t)i * n;
+    const double* rb = Be + (size_t)i * t;
+    double s = 0.0;
+    for (int k = lane; k < n; k += 64) s += ra[k] * ze[k];
+    for (int k = lane; k < t; k += 64) s += rb[k] * ue[k];
+    s = wave_sum(s);
+    if (lane == 0) {
+      const double f = F[(size_t)e * n + i];
+      const double v = f - s;
+      rF[(size_t)e * n + i] = v;
+      srf += v * v;
+      sf += f * f;
+    }
+  }
+  for (int i = wv; i < t; i += LWAVES) {
+    const double* rc = Ce + (size_t)i * n;
+    const double* rd = De + (size_t)i * t;
+    double s = 0.0;
+    for (int k = lane; k < n; k += 64) s += rc[k] * ze[k];
+    for (int k = lane; k < t; k += 64) s += rd[k] * ue[k];
+    s = wave_sum(s);
+    if (lane == 0) q[(size_t)e * t + i] = s;
+  }
+  if (lane == 0) { acc[2 * wv] = srf; acc[2 * wv + 1] = sf; }
+  __syncthreads();
+  if (tid == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < LWAVES; ++k) { a0 += acc[2 * k]; a1 += acc[2 * k + 1]; }
+    part_rf[e] = a0;
+    part_f[e] = a1;
+  }
+}
+
+// rG = G - sum_e P_e^T q_e (ascending e) and per-face sums of rG^2, G^2.
+__global__ __launch_bounds__(128) void residual_face_kernel(int b, int t, const int32_t* face_src, const double* q,
+                                                            const double* G, double* rG, double* part_rg,
+                                                            double* part_g) {
+  __shared__ double red[2];
+  const int f = blockIdx.x, l = threadIdx.x;
+  double v = 0.0, g = 0.0;
+  if (l < b) {
+    const size_t i = (size_t)f * b + l;
+    g = G[i];
+    v = g;
+    for (int k = 0; k < 2; ++k) {
+      const int src = face_src[2 * f + k];
+      if (src >= 0) v -= q[(size_t)(src / 6) * t + (src % 6) * b + l];
+    }
+    rG[i] = v;
+  }
+  const double s1 = wave_sum(l < 64 ? v * v : 0.0) + 0.0;
+  const double s2 = wave_sum(l < 64 ? g * g : 0.0);
+  const double s3 = wave_sum(l >= 64 ? v * v : 0.0);
+  const double s4 = wave_sum(l >= 64 ? g * g : 0.0);
+  if (l == 64) { red[0] = s3; red[1] = s4; }
+  __syncthreads();
+  if (l == 0) {
+    part_rg[f] = s1 + red[0];
+    part_g[f] = s2 + red[1];
+  }
+}
+
+// sums[k] = sum over i < len_k of part_k[i], fixed order, one wave each.
+__global__ void sum4_kernel(const double* p0, int64_t n0, const double* p1, int64_t n1, const double* p2, int64_t n2,
+                            const double* p3, int64_t n3, double* sums) {
+  const int k = blockIdx.x, lane = threadIdx.x;
+  const double* p = k == 0 ? p0 : k == 1 ? p1 : k == 2 ? p2 : p3;
+  const int64_t n = k == 0 ? n0 : k == 1 ? n1 : k == 2 ? n2 : n3;
+  double s = 0.0;
+  for (int64_t i = lane; i < n; i += 64) s += p[i];
+  s = wave_sum(s);
+  if (lane == 0) sums[k] = s;
+}
+
+}  // namespace iedg
+
+using namespace iedg;
+
+extern "C" iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, int32_t n_local, iedg_prec prec,
+                                            const void* LU, const void* U12, const double* w, const double* uhat,
+                                            double* z, hipStream_t stream) {
+  if (!ctx || !mesh || !LU || !U12 || !w || !uhat || !z || n_local <= 0) return IEDG_ERR_INVALID_ARG;
+  const int n = n_local, t = mesh->t, b = mesh->b;
+  const size_t smem = sizeof(double) * (t + n + 64 * 65);
+  if (prec == IEDG_F64) {
+    auto k = backsolve_kernel<double>;
+    IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
+                       (const double*)LU, (const double*)U12, w, uhat, z);
+  } else {
+    auto k = backsolve_kernel<float>;
+    IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
+                       (const float*)LU, (const float*)U12, w, uhat, z);
+  }
+  IEDG_LAUNCH_CHECK(ctx, "backsolve launch");
+  return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int32_t n_local, const double* A,
+                                          const double* B, const double* C, const double* D, const double* F,
+                                          const double* G, const double* z, const double* uhat, double* rF,
+                                          double* rG, double* sums, hipStream_t stream) {
+  if (!ctx || !mesh || !A || !B || !C || !D || !F || !G || !z || !uhat || !rF || !rG || !sums || n_local <= 0)
+    return IEDG_ERR_INVALID_ARG;
+  const int n = n_local, t = mesh->t, b = mesh->b, E = mesh->n_elem, NF = mesh->n_face;
+  // scratch: q [E][t], partials 2E + 2NF
+  const size_t need = sizeof(double) * ((size_t)E * t + 2 * (size_t)E + 2 * (size_t)NF) + 1024;
+  iedg_status st = ensure_work(ctx, need);
+  if (st != IEDG_OK) return st;
+  double* q = static_cast<double*>(ctx->work);
+  double* prf = q + (size_t)E * t;
+  double* pf = prf + E;
+  double* prg = pf + E;
+  double* pg = prg + NF;
+  const size_t smem = sizeof(double) * (t + n + 3 * LWAVES);
+  IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(residual_elem_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  hipLaunchKernelGGL(residual_elem_kernel, dim3(E), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces, A, B, C, D,
+                     F, z, uhat, rF, q, prf, pf);
+  hipLaunchKernelGGL(residual_face_kernel, dim3(NF), dim3(128), 0, stream, b, t, mesh->d_face_src, q, G, rG, prg, pg);
+  hipLaunchKernelGGL(sum4_kernel, dim3(4), dim3(64), 0, stream, prf, (int64_t)E, prg, (int64_t)NF, pf, (int64_t)E, pg,
+                     (int64_t)NF, sums);
+  IEDG_LAUNCH_CHECK(ctx, "residual launch");
+  return IEDG_OK;
+}

@@ -1,0 +1,34 @@
+// Trace mesh: block pattern of K, element->BSR scatter map, BILU(0) schedule.
+#pragma once
+
+#include "common.h"
+
+struct iedg_mesh_s {
+  iedg_context ctx = nullptr;
+  int32_t n_elem = 0, n_face = 0, b = 0, t = 0;
+  int64_t n_trace = 0, nnzb = 0;
+  int32_t n_levels = 0;
+  int64_t n_lslots = 0, n_updates = 0;
+
+  // host copies (exported by iedg_mesh_query)
+  std::vector<int32_t> order;       // row i -> face
+  std::vector<int32_t> pos;         // face -> row
+  std::vector<int32_t> level_ptr;   // [n_levels + 1] into level_rows
+  std::vector<int32_t> level_rows;  // rows grouped by level, ascending within a level
+  std::vector<int32_t> row_ptr;     // [n_face + 1]
+  std::vector<int32_t> col_face;    // [nnzb]
+
+  // device copies
+  int32_t* d_elem_faces = nullptr;  // [E][6]
+  int32_t* d_row_face = nullptr;    // [n_face]
+  int32_t* d_row_ptr = nullptr;     // [n_face + 1]
+  int32_t* d_col_face = nullptr;    // [nnzb]
+  int32_t* d_diag_slot = nullptr;   // [n_face]
+  int32_t* d_level_rows = nullptr;  // [n_face]
+  int32_t* d_asm_src = nullptr;     // [nnzb][2]: e*36 + a*6 + c or -1
+  int32_t* d_face_src = nullptr;    // [n_face][2]: e*6 + a or -1
+  int32_t* d_ilu_lptr = nullptr;    // [n_face + 1] into ilu_l (per row)
+  int32_t* d_ilu_l = nullptr;       // [n_lslots][2]: slot (i,k), diag slot of k
+  int32_t* d_ilu_uptr = nullptr;    // [n_lslots + 1] into ilu_upd
+  int32_t* d_ilu_upd = nullptr;     // [n_updates][2]: slot (k,j), slot (i,j)
+};

@@ -1,0 +1,409 @@
+// Block-sparse trace system on gfx950: assembly of K and R (section 2.2.1,
+// eq. LS), BILU(0) factorisation and its triangular sweeps, and the BSR
+// matrix-vector product (section 2.2.2).  Blocks are b x b, column-major,
+// stored in the row order of the mesh's ordering (see iedg.h).
+#include "common.h"
+#include "mesh.h"
+
+namespace iedg {
+
+constexpr int STHR = 256;
+
+// ---- assembly ----------------------------------------------------------
+// One workgroup per BSR block: gather the (one or two) element sub-blocks
+// Ke_e[a*b:(a+1)*b, c*b:(c+1)*b] (row-major t x t), sum in ascending element
+// order and write the block transposed to column-major through LDS.
+template <typename T>
+__global__ __launch_bounds__(STHR) void assemble_k_kernel(int b, int t, const int32_t* asm_src, const T* Ke,
+                                                          T* Kbsr) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);  // b x (b+1)
+  const int64_t s = blockIdx.x;
+  const int src0 = asm_src[2 * s], src1 = asm_src[2 * s + 1];
+  const int bb = b * b;
+  const size_t tt = (size_t)t * t;
+  const T* p0 = Ke + (size_t)(src0 / 36) * tt + (size_t)((src0 % 36) / 6) * b * t + (size_t)(src0 % 6) * b;
+  const T* p1 = src1 >= 0 ? Ke + (size_t)(src1 / 36) * tt + (size_t)((src1 % 36) / 6) * b * t + (size_t)(src1 % 6) * b
+                          : nullptr;
+  for (int i = threadIdx.x; i < bb; i += STHR) {
+    const int rr = i / b, cc = i % b;
+    T v = p0[(size_t)rr * t + cc];
+    if (p1) v += p1[(size_t)rr * t + cc];
+    tile[rr * (b + 1) + cc] = v;
+  }
+  __syncthreads();
+  T* out = Kbsr + (size_t)s * bb;
+  for (int i = threadIdx.x; i < bb; i += STHR) {
+    const int cc = i / b, rr = i % b;
+    out[i] = tile[rr * (b + 1) + cc];
+  }
+}
+
+// R[f*b + l] = G[f*b + l] + sum over elements e (ascending) of r_e[a*b + l].
+__global__ void assemble_r_kernel(int n_face, int b, int t, const int32_t* face_src, const double* r,
+                                  const double* G, double* R) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_face * b) return;
+  const int f = (int)(i / b), l = (int)(i % b);
+  double v = G ? G[i] : 0.0;
+  if (r) {
+    for (int k = 0; k < 2; ++k) {
+      const int src = face_src[2 * f + k];
+      if (src >= 0) v += r[(size_t)(src / 6) * t + (src % 6) * b + l];
+    }
+  }
+  R[i] = v;
+}
+
+// ---- BSR products --------------------------------------------------------
+// Threads form G = STHR / b groups of b lanes; lane rr of group g
+// accumulates row rr over blocks g, g+G, ... of a slot range.  Reads of a
+// column-major block by consecutive rr are contiguous.
+template <typename T>
+__device__ inline double block_row_sum(int b, const T* blocks, const int32_t* col_face, int s0, int s1,
+                                       const double* x, int g, int G, int rr) {
+  double acc = 0.0;
+  if (g >= G) return 0.0;
+  for (int s = s0 + g; s < s1; s += G) {
+    const T* blk = blocks + (size_t)s * b * b + rr;
+    const double* xs = x + (size_t)col_face[s] * b;
+    int cc = 0;
+    double a0 = 0.0, a1 = 0.0;
+    for (; cc + 1 < b; cc += 2) {
+      a0 += (double)blk[(size_t)cc * b] * xs[cc];
+      a1 += (double)blk[(size_t)(cc + 1) * b] * xs[cc + 1];
+    }
+    if (cc < b) a0 += (double)blk[(size_t)cc * b] * xs[cc];
+    acc += a0 + a1;
+  }
+  return acc;
+}
+
+// Reduce the G group partials of row rr into red[rr]; fixed order.
+__device__ inline void group_reduce(double* red, int b, int G, int g, int rr, double v) {
+  if (g < G) red[g * b + rr] = v;
+  __syncthreads();
+  if (threadIdx.x < b) {
+    double s = red[threadIdx.x];
+    for (int k = 1; k < G; ++k) s += red[k * b + threadIdx.x];
+    red[G * b + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// y = K x  (mode 0)   or   y = rhs - K x  (mode 1)
+template <typename T>
+__global__ __launch_bounds__(STHR) void spmv_kernel(int b, const int32_t* row_face, const int32_t* row_ptr,
+                                                    const int32_t* col_face, const T* K, const double* x,
+                                                    const double* rhs, double* y, int mode) {
+  __shared__ double red[STHR + 128];
+  const int i = blockIdx.x;
+  const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
+  const double v = block_row_sum<T>(b, K, col_face, row_ptr[i], row_ptr[i + 1], x, g, G, rr);
+  group_reduce(red, b, G, g, rr, v);
+  if (threadIdx.x < b) {
+    const size_t o = (size_t)row_face[i] * b + threadIdx.x;
+    const double kx = red[G * b + threadIdx.x];
+    y[o] = mode == 0 ? kx : rhs[o] - kx;
+  }
+}
+
+// One level of the BILU(0) sweeps.  Forward (upper = 0): y_i = x_i - sum
+// over lower slots L_ik y_k.  Backward (upper = 1): y_i = Uinv_i (y_i - sum
+// over upper slots U_ij y_j).  x may equal y.
+template <typename T>
+__global__ __launch_bounds__(STHR) void sweep_kernel(int b, const int32_t* rows, const int32_t* row_face,
+                                                     const int32_t* row_ptr, const int32_t* diag_slot,
+                                                     const int32_t* col_face, const T* M, const double* x,
+                                                     double* y, int upper) {
+  __shared__ double red[STHR + 128];
+  const int i = rows[blockIdx.x];
+  const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
+  const int ds = diag_slot[i];
+  const int s0 = upper ? ds + 1 : row_ptr[i];
+  const int s1 = upper ? row_ptr[i + 1] : ds;
+  const double v = block_row_sum<T>(b, M, col_face, s0, s1, y, g, G, rr);
+  group_reduce(red, b, G, g, rr, v);
+  const size_t o = (size_t)row_face[i] * b;
+  if (!upper) {
+    if (threadIdx.x < b) y[o + threadIdx.x] = x[o + threadIdx.x] - red[G * b + threadIdx.x];
+    return;
+  }
+  // s = x_i - sum  ->  red[0:b]; then y_i = Uinv s
+  __shared__ double svec[128];
+  if (threadIdx.x < b) svec[threadIdx.x] = x[o + threadIdx.x] - red[G * b + threadIdx.x];
+  __syncthreads();
+  double acc = 0.0;
+  if (g < G) {
+    const T* blk = M + (size_t)ds * b * b + rr;
+    for (int cc = g; cc < b; cc += G) acc += (double)blk[(size_t)cc * b] * svec[cc];
+  }
+  group_reduce(red, b, G, g, rr, acc);
+  if (threadIdx.x < b) y[o + threadIdx.x] = red[G * b + threadIdx.x];
+}
+
+// ---- BILU(0) factorisation ------------------------------------------------
+// Product of two b x b column-major blocks with FP64/FP32 MFMA.  Tiles of
+// 16 x 16 are dealt to the 4 waves round-robin; each wave keeps up to 8 tile
+// accumulators (b <= 128).  mode 0: C = A * B (C may alias A: all products are
+// formed before any store, separated by a barrier); mode 1: C -= A * B.
+template <typename T>
+__device__ void block_mm(int b, const T* A, const T* B, T* C, int mode) {
+  typedef Mfma<T> MF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nt = (b + 15) / 16, ntiles = nt * nt;
+  typename MF::acc_t acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = MF::zero();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int tI = wv + 4 * q;
+    if (tI < ntiles) {
+      const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+      const int ia = i0 + li, jb = j0 + li;
+      for (int k0 = 0; k0 < b; k0 += 4) {
+        const int k = k0 + lk;
+        const T av = (ia < b && k < b) ? A[(size_t)k * b + ia] : T(0);
+        const T bv = (jb < b && k < b) ? B[(size_t)jb * b + k] : T(0);
+        acc[q] = MF::mac(av, bv, acc[q]);
+      }
+    }
+  }
+  if (mode == 0) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int tI = wv + 4 * q;
+    if (tI < ntiles) {
+      const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + MF::row(lane, v), j = j0 + li;
+        if (i < b && j < b) {
+          T* c = C + (size_t)j * b + i;
+          *c = mode == 0 ? acc[q][v] : *c - acc[q][v];
+        }
+      }
+    }
+  }
+}
+
+// In-place Gauss-Jordan inverse with partial (row) pivoting of a b x b
+// column-major block held in LDS as row-major a[r * (b+1) + c].
+template <typename T>
+__device__ bool gj_invert(T* a, int b, int* piv, double* rv, int* ri) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int ld = b + 1;
+  bool ok = true;
+  for (int k = 0; k < b; ++k) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int r = k + lane; r < b; r += 64) {
+        const double v = fabs((double)a[r * ld + k]);
+        if (v > best) { best = v; bi = r; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bi, off, kWave);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (lane == 0) { rv[0] = best; ri[0] = bi; piv[k] = bi; }
+    }
+    __syncthreads();
+    const int p = ri[0];
+    if (!(rv[0] > 0.0) || !isfinite(rv[0])) ok = false;
+    if (p != k)
+      for (int c = tid; c < b; c += STHR) {
+        const T tmp = a[k * ld + c];
+        a[k * ld + c] = a[p * ld + c];
+        a[p * ld + c] = tmp;
+      }
+    __syncthreads();
+    const T pinv = T(1) / a[k * ld + k];
+    __syncthreads();
+    if (tid == 0) a[k * ld + k] = T(1);
+    __syncthreads();
+    for (int c = tid; c < b; c += STHR) a[k * ld + c] *= pinv;
+    __syncthreads();
+    // eliminate column k from every other row; factors read before update
+    for (int q = tid; q < b * b; q += STHR) {
+      const int r = q / b, c = q % b;
+      if (r != k && c != k) a[r * ld + c] -= a[r * ld + k] * a[k * ld + c];
+    }
+    __syncthreads();
+    for (int r = tid; r < b; r += STHR)
+      if (r != k) a[r * ld + k] = -a[r * ld + k] * a[k * ld + k];
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  for (int k = b - 1; k >= 0; --k) {
+    const int p = piv[k];
+    if (p != k)
+      for (int r = tid; r < b; r += STHR) {
+        const T tmp = a[r * ld + k];
+        a[r * ld + k] = a[r * ld + p];
+        a[r * ld + p] = tmp;
+      }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// One level of BILU(0): one workgroup per block row i of the level.
+template <typename T>
+__global__ __launch_bounds__(STHR) void ilu0_level_kernel(int b, const int32_t* rows, const int32_t* diag_slot,
+                                                          const int32_t* lptr, const int32_t* lslot,
+                                                          const int32_t* uptr, const int32_t* upd, T* M,
+                                                          DeviceStatus* status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* a = reinterpret_cast<T*>(smem_raw);                        // b x (b+1)
+  int* piv = reinterpret_cast<int*>(a + (size_t)b * (b + 1));   // b
+  double* rv = reinterpret_cast<double*>(piv + 128);            // 1
+  int* ri = reinterpret_cast<int*>(rv + 1);                     // 1
+  const int i = rows[blockIdx.x];
+  const size_t bb = (size_t)b * b;
+  for (int l = lptr[i]; l < lptr[i + 1]; ++l) {
+    const int sik = lslot[2 * l], dk = lslot[2 * l + 1];
+    // L_ik = A_ik * Uinv_k
+    block_mm<T>(b, M + sik * bb, M + dk * bb, M + sik * bb, 0);
+    __syncthreads();
+    for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
+      const int skj = upd[2 * u], sij = upd[2 * u + 1];
+      block_mm<T>(b, M + sik * bb, M + skj * bb, M + sij * bb, 1);
+    }
+    __syncthreads();
+  }
+  // pivot block: invert in place
+  T* D = M + diag_slot[i] * bb;
+  for (int q = threadIdx.x; q < b * b; q += STHR) {
+    const int c = q / b, r = q % b;
+    a[r * (b + 1) + c] = D[q];
+  }
+  __syncthreads();
+  const bool ok = gj_invert<T>(a, b, piv, rv, ri);
+  if (!ok && threadIdx.x == 0) latch_status(status, IEDG_ERR_SINGULAR, i);
+  for (int q = threadIdx.x; q < b * b; q += STHR) {
+    const int c = q / b, r = q % b;
+    D[q] = a[r * (b + 1) + c];
+  }
+}
+
+template <typename T>
+static size_t elem_size() { return sizeof(T); }
+
+static size_t prec_size(iedg_prec p) { return p == IEDG_F64 ? sizeof(double) : sizeof(float); }
+
+}  // namespace iedg
+
+using namespace iedg;
+
+namespace iedg {
+
+iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x,
+                        const double* rhs, double* y, int mode, hipStream_t stream) {
+  if (kprec == IEDG_F64)
+    hipLaunchKernelGGL(spmv_kernel<double>, dim3(m->n_face), dim3(STHR), 0, stream, m->b, m->d_row_face,
+                       m->d_row_ptr, m->d_col_face, (const double*)K, x, rhs, y, mode);
+  else
+    hipLaunchKernelGGL(spmv_kernel<float>, dim3(m->n_face), dim3(STHR), 0, stream, m->b, m->d_row_face,
+                       m->d_row_ptr, m->d_col_face, (const float*)K, x, rhs, y, mode);
+  IEDG_LAUNCH_CHECK(ctx, "spmv launch");
+  return IEDG_OK;
+}
+
+// y = M^{-1} x : forward sweep over levels, then backward sweep in reverse.
+iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
+                              double* y, hipStream_t stream) {
+  for (int dir = 0; dir < 2; ++dir) {
+    for (int li = 0; li < m->n_levels; ++li) {
+      const int l = dir == 0 ? li : m->n_levels - 1 - li;
+      const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
+      const double* src = dir == 0 ? x : y;
+      if (mprec == IEDG_F64)
+        hipLaunchKernelGGL(sweep_kernel<double>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
+                           m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const double*)M, src, y,
+                           dir);
+      else
+        hipLaunchKernelGGL(sweep_kernel<float>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
+                           m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const float*)M, src, y,
+                           dir);
+    }
+  }
+  IEDG_LAUNCH_CHECK(ctx, "ilu0 sweep launch");
+  return IEDG_OK;
+}
+
+}  // namespace iedg
+
+extern "C" {
+
+iedg_status iedg_assemble(iedg_context ctx, iedg_mesh m, iedg_prec prec, const void* Ke, const double* r,
+                          const double* G, void* Kbsr, double* R, hipStream_t stream) {
+  if (!ctx || !m) return IEDG_ERR_INVALID_ARG;
+  if ((Ke == nullptr) != (Kbsr == nullptr)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "assemble: Ke and Kbsr go together");
+  if ((r || G) && !R) return set_error(ctx, IEDG_ERR_INVALID_ARG, "assemble: R missing");
+  if (prec != IEDG_F64 && prec != IEDG_F32 && prec != IEDG_BF16)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "assemble: precision");
+  if (Ke) {
+    const size_t smem = prec_size(prec) * m->b * (m->b + 1);
+    if (prec == IEDG_F64) {
+      auto k = assemble_k_kernel<double>;
+      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->d_asm_src, (const double*)Ke,
+                         (double*)Kbsr);
+    } else {
+      auto k = assemble_k_kernel<float>;
+      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->d_asm_src, (const float*)Ke,
+                         (float*)Kbsr);
+    }
+    IEDG_LAUNCH_CHECK(ctx, "assemble K launch");
+  }
+  if (R) {
+    const int64_t total = m->n_trace;
+    hipLaunchKernelGGL(assemble_r_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, m->n_face,
+                       m->b, m->t, m->d_face_src, r, G, R);
+    IEDG_LAUNCH_CHECK(ctx, "assemble R launch");
+  }
+  return IEDG_OK;
+}
+
+iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh m, iedg_prec prec, const void* Kbsr, void* Mbsr,
+                             hipStream_t stream) {
+  if (!ctx || !m || !Kbsr || !Mbsr) return IEDG_ERR_INVALID_ARG;
+  const size_t es = prec_size(prec);
+  if (Kbsr != Mbsr)
+    IEDG_HIP(ctx, hipMemcpyAsync(Mbsr, Kbsr, es * m->nnzb * m->b * m->b, hipMemcpyDeviceToDevice, stream));
+  const size_t smem = es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
+  for (int l = 0; l < m->n_levels; ++l) {
+    const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
+    if (prec == IEDG_F64) {
+      auto k = ilu0_level_kernel<double>;
+      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                         m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (double*)Mbsr, ctx->d_status);
+    } else {
+      auto k = ilu0_level_kernel<float>;
+      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+      hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                         m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (float*)Mbsr, ctx->d_status);
+    }
+    IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
+  }
+  return IEDG_OK;
+}
+
+iedg_status iedg_spmv(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x, double* y,
+                      hipStream_t stream) {
+  if (!ctx || !m || !K || !x || !y) return IEDG_ERR_INVALID_ARG;
+  return spmv_launch(ctx, m, kprec, K, x, nullptr, y, 0, stream);
+}
+
+iedg_status iedg_ilu0_apply(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
+                            double* y, hipStream_t stream) {
+  if (!ctx || !m || !M || !x || !y) return IEDG_ERR_INVALID_ARG;
+  return ilu0_apply_launch(ctx, m, mprec, M, x, y, stream);
+}
+
+}  // extern "C"

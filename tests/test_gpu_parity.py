@@ -1,0 +1,287 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded
+inputs.  Tolerances follow the FP64 rounding of each step (documented in the
+design notes): element Schur complements and right-hand sides <= 1e-12
+relative, assembly bit-exact, BILU(0) factors <= 1e-11, products <= 1e-13,
+solutions within condition * rtol."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle.assembly import matvec
+from synth import StructuredHexMesh, ElementSpec, element_inputs, trace_rhs, SEED_BASE
+from synth.matrices import workload
+
+from helpers import host_case, dense_uncondensed
+from gpu_util import dev, stack, host_blocks_to_dev, bsr_from_oracle, oracle_from_bsr, rel
+
+pytestmark = pytest.mark.gpu
+
+api = pytest.importorskip("paper_1605_01020_amd.api")
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = api.Context()
+    yield c
+    torch.cuda.synchronize()
+
+
+def _mesh(ctx, m, spec, ordering="colour"):
+    return api.Mesh(ctx, m.elem_faces(), m.n_face, spec.b, ordering=ordering)
+
+
+def _tmesh(m, spec):
+    return oracle.TraceMesh(m.elem_faces(), m.n_face, spec.b)
+
+
+CASES = [((1, 1, 1), 1), ((2, 2, 1), 2), ((2, 1, 1), 3)]
+
+
+def test_device_generator_matches_host(ctx):
+    import synth.device as sd
+    from synth.philox import philox4x32_10
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    seed = SEED_BASE + 7
+    _say("philox words")
+    d = sd.philox_words(ctr, seed)
+    h = np.stack(philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], seed & 0xFFFFFFFF, seed >> 32), axis=1)
+    assert np.array_equal(d, h)
+    spec = ElementSpec(2)
+    _say("element blocks p=2")
+    blk = sd.gen_blocks(spec, SEED_BASE, 3, 2, which="ABCDF", elem0=5)
+    for e in range(2):
+        host = element_inputs(spec, SEED_BASE, 3, 5 + e)
+        for k in "ABCDF":
+            np.testing.assert_allclose(blk[k][e].cpu().numpy().reshape(host[k].shape), host[k], rtol=2e-14, atol=2e-15)
+    G = sd.gen_trace_rhs(spec, SEED_BASE, 3, 40)
+    np.testing.assert_allclose(G.cpu().numpy(), trace_rhs(spec, SEED_BASE, 3, 40), rtol=2e-14, atol=2e-15)
+
+
+@pytest.mark.parametrize("dims,p", CASES)
+def test_condense_parity(ctx, dims, p):
+    m, spec, blocks, G = host_case(dims, p)
+    _say(f"condense {dims} p={p} n={spec.n} t={spec.t}")
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"])
+    ctx.sync_status()
+    for e, blk in enumerate(blocks):
+        Ke, re, _ = oracle.condense_element(blk["A"], blk["B"], blk["C"], blk["D"], blk["F"])
+        assert rel(fac["Ke"][e].cpu().numpy(), Ke) <= 1e-12
+        assert rel(fac["r"][e].cpu().numpy(), re) <= 1e-12
+        # factor properties that hold for any partial-pivoting sequence
+        LU = fac["LU"][e].cpu().numpy()
+        perm = fac["perm"][e].cpu().numpy()
+        assert sorted(perm.tolist()) == list(range(spec.n))
+        L = np.tril(LU, -1) + np.eye(spec.n)
+        U = np.triu(LU)
+        PA = blk["A"][perm]
+        assert rel(L @ U, PA) <= 1e-13
+        assert np.abs(np.tril(LU, -1)).max() <= 1.0 + 1e-12  # partial pivoting bound
+        assert rel(L @ fac["U12"][e].cpu().numpy(), blk["B"][perm]) <= 1e-13
+        assert rel(L @ fac["w"][e].cpu().numpy(), blk["F"][perm]) <= 1e-13
+        assert rel(fac["L21"][e].cpu().numpy() @ U, blk["C"]) <= 1e-13
+
+
+def test_condense_without_rhs(ctx):
+    m, spec, blocks, G = host_case((1, 1, 1), 1)
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], None)
+    Ke, _, _ = oracle.condense_element(blocks[0]["A"], blocks[0]["B"], blocks[0]["C"], blocks[0]["D"])
+    assert rel(fac["Ke"][0].cpu().numpy(), Ke) <= 1e-12
+    assert "w" not in fac
+
+
+def test_order_and_pattern_match_oracle(ctx):
+    for dims in [(2, 2, 2), (3, 2, 4), (4, 4, 4)]:
+        m = StructuredHexMesh(*dims)
+        tm = oracle.TraceMesh(m.elem_faces(), m.n_face, 1)
+        for ordering, ref in (("colour", oracle.greedy_colour_order(tm)), ("natural", oracle.natural_order(tm))):
+            mesh = api.Mesh(ctx, m.elem_faces(), m.n_face, 5, ordering=ordering)
+            q = mesh.query()
+            assert np.array_equal(q["order"], ref)
+            lev = oracle.level_sets(tm, ref)
+            assert mesh.n_levels == lev.max() + 1
+            assert mesh.nnzb == tm.nnzb() == m.n_face + 30 * m.n_elem
+            for i, f in enumerate(q["order"]):
+                cols = q["col_face"][q["row_ptr"][i]:q["row_ptr"][i + 1]]
+                assert sorted(cols.tolist()) == tm.pattern[f]
+
+
+@pytest.mark.parametrize("dims,p", [((2, 2, 2), 1), ((2, 2, 1), 2)])
+def test_assemble_bit_exact(ctx, dims, p):
+    m, spec, blocks, G = host_case(dims, p)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec)
+    Ks, rs = oracle.condense_all(blocks)
+    K, R = oracle.assemble(tm, Ks, rs, G)
+    Kbsr, Rd = api.assemble(ctx, mesh, Ke=dev(np.stack(Ks)), r=dev(np.stack(rs)), G=dev(G))
+    q = mesh.query()
+    assert np.array_equal(Kbsr.cpu().numpy(), bsr_from_oracle(mesh, K, q))
+    assert np.array_equal(Rd.cpu().numpy(), R)
+
+
+@pytest.mark.parametrize("ordering", ["colour", "natural"])
+def test_ilu0_and_products_parity(ctx, ordering):
+    m, spec, blocks, G = host_case((2, 2, 2), 1)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec, ordering)
+    q = mesh.query()
+    Ks, rs = oracle.condense_all(blocks)
+    K, R = oracle.assemble(tm, Ks, rs, G)
+    _say(f"ilu0 {ordering}")
+    Kd = dev(bsr_from_oracle(mesh, K, q))
+    Md = api.factor_ilu0(ctx, mesh, Kd)
+    ctx.sync_status()
+    fac = oracle.bilu0(tm, K, q["order"])
+    got = oracle_from_bsr(mesh, Md.cpu().numpy(), q)
+    scale = max(np.abs(v).max() for v in K.values())
+    for key, Lb in fac["L"].items():
+        assert np.abs(got[key] - Lb).max() <= 1e-11 * scale
+    for key, Ub in fac["U"].items():
+        if key[0] != key[1]:
+            assert np.abs(got[key] - Ub).max() <= 1e-11 * scale
+    for i, Ui in fac["Uinv"].items():
+        assert np.abs(got[(i, i)] - Ui).max() <= 1e-11 * np.abs(Ui).max()
+    x = np.random.default_rng(3).standard_normal(tm.n_trace)
+    y = api.spmv(ctx, mesh, Kd, dev(x)).cpu().numpy()
+    assert rel(y, matvec(tm, K, x)) <= 1e-14
+    z = api.ilu0_apply(ctx, mesh, Md, dev(x)).cpu().numpy()
+    assert rel(z, oracle.bilu0_apply(tm, fac, x)) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,p", [((2, 2, 2), 1), ((2, 2, 1), 2)])
+def test_full_solve_matches_dense(ctx, dims, p):
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    m, spec, blocks, G = host_case(dims, p)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec)
+    d = host_blocks_to_dev(blocks)
+    _say(f"full solve {dims} p={p}")
+    s = NewtonStepSolver(ctx, mesh, spec.n, restart=50)
+    z, uhat, info = s.solve_fp64(d["A"], d["B"], d["C"], d["D"], d["F"], dev(G), rtol=1e-13)
+    ctx.sync_status()
+    M, rhs = dense_uncondensed(tm, blocks, G)
+    sol = np.linalg.solve(M, rhs)
+    mine = np.concatenate([z.cpu().numpy().ravel(), uhat.cpu().numpy()])
+    assert rel(mine, sol) <= 1e-11
+    # the FP64 residual kernel against the dense residual
+    rF, rG, sums = api.residual_full(ctx, mesh, d["A"], d["B"], d["C"], d["D"], d["F"], dev(G), z, uhat)
+    r_dense = rhs - M @ mine
+    E, n = tm.n_elem, spec.n
+    assert np.abs(rF.cpu().numpy().ravel() - r_dense[:E * n]).max() <= 1e-12
+    assert np.abs(rG.cpu().numpy() - r_dense[E * n:]).max() <= 1e-12
+    s_ = sums.cpu().numpy()
+    assert abs(s_[2] - sum(float(b["F"] @ b["F"]) for b in blocks)) <= 1e-12 * s_[2]
+    assert abs(s_[3] - float(G @ G)) <= 1e-12 * s_[3]
+
+
+def test_backsolve_and_condense_rhs_parity(ctx):
+    m, spec, blocks, G = host_case((2, 2, 1), 2)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec)
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"])
+    uhat = np.random.default_rng(5).standard_normal(tm.n_trace)
+    z = api.backsolve_local(ctx, mesh, fac, dev(uhat)).cpu().numpy()
+    for e, blk in enumerate(blocks):
+        ref = oracle.backsolve_element(blk["A"], blk["B"], blk["F"], uhat[tm.element_dofs(e)])
+        assert rel(z[e], ref) <= 1e-12
+    F2 = [element_inputs(spec, SEED_BASE, 0, e, rhs=1, which="F")["F"] for e in range(m.n_elem)]
+    w, r = api.condense_rhs(ctx, fac, dev(np.stack(F2)))
+    for e, blk in enumerate(blocks):
+        _, re, _ = oracle.condense_element(blk["A"], blk["B"], blk["C"], blk["D"], F2[e])
+        assert rel(r[e].cpu().numpy(), re) <= 1e-12
+
+
+@pytest.fixture(scope="module")
+def cfg0_oracle():
+    wl = workload(0)
+    mc = wl.meshes[0]
+    m, spec, blocks, G = host_case(mc.dims, mc.p, seed=wl.seed)
+    tm = _tmesh(m, spec)
+    res = oracle.newton_step_solve(tm, blocks, G, restart=wl.restart, rtol=wl.rtol)
+    return wl, m, spec, tm, blocks, G, res
+
+
+def test_config0_fp64_solve(ctx, cfg0_oracle):
+    import synth.device as sd
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    wl, m, spec, tm, blocks, G, ref = cfg0_oracle
+    mesh = _mesh(ctx, m, spec)
+    _say("config 0 fp64 solve (device-generated inputs)")
+    d = sd.gen_blocks(spec, wl.seed, 0, m.n_elem, which="ABCDF")
+    Gd = sd.gen_trace_rhs(spec, wl.seed, 0, m.n_face)
+    s = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
+    z, uhat, info = s.solve_fp64(d["A"], d["B"], d["C"], d["D"], d["F"], Gd, rtol=wl.rtol)
+    ctx.sync_status()
+    assert info["converged"] and info["rel_resid"] <= wl.rtol
+    assert info["iters"] == ref["info"]["iters"]
+    u = uhat.cpu().numpy()
+    assert rel(u, ref["uhat"]) <= 5e-10
+    zz = z.cpu().numpy()
+    assert rel(zz, np.stack(ref["z"])) <= 5e-10
+    _, _, sums = api.residual_full(ctx, mesh, d["A"], d["B"], d["C"], d["D"], d["F"], Gd, z, uhat)
+    s_ = sums.cpu().numpy()
+    assert np.sqrt((s_[0] + s_[1]) / (s_[2] + s_[3])) <= wl.rtol
+    # bitwise reproducible
+    z2, u2, _ = s.solve_fp64(d["A"], d["B"], d["C"], d["D"], d["F"], Gd, rtol=wl.rtol)
+    assert torch.equal(u2, uhat) and torch.equal(z2, z)
+
+
+def test_config0_mixed_fp32_refinement(ctx, cfg0_oracle):
+    import synth.device as sd
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    from paper_1605_01020_amd import F32
+    wl, m, spec, tm, blocks, G, ref = cfg0_oracle
+    mesh = _mesh(ctx, m, spec)
+    _say("config 0 mixed fp32 + refinement")
+    d = sd.gen_blocks(spec, wl.seed, 0, m.n_elem, which="ABCDF")
+    Gd = sd.gen_trace_rhs(spec, wl.seed, 0, m.n_face)
+    s = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
+    z, uhat, info = s.solve_mixed(d["A"], d["B"], d["C"], d["D"], d["F"], Gd, tol=1e-8, prec=F32)
+    ctx.sync_status()
+    assert info["converged_full"], info
+    # error against the FP64 oracle solution
+    assert rel(uhat.cpu().numpy(), ref["uhat"]) <= 1e-7
+    assert rel(z.cpu().numpy(), np.stack(ref["z"])) <= 1e-7
+
+
+def test_singular_pivot_reported(ctx):
+    m, spec, blocks, G = host_case((1, 1, 1), 1)
+    A = stack(blocks, "A").copy()
+    A[0, 7, :] = 0.0
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, dev(A), d["B"], d["C"], d["D"], d["F"])
+    with pytest.raises(api.IedgError) as ei:
+        ctx.sync_status()
+    assert ei.value.status == -2 and ei.value.index == 0
+    ctx.sync_status()  # cleared
+
+
+def test_gmres_failure_paths(ctx):
+    m, spec, blocks, G = host_case((2, 2, 2), 1)
+    mesh = _mesh(ctx, m, spec)
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"])
+    K, R = api.assemble(ctx, mesh, Ke=fac["Ke"], r=fac["r"], G=dev(G))
+    M = api.factor_ilu0(ctx, mesh, K)
+    x, info = api.gmres_solve(ctx, mesh, K, M, R, restart=5, rtol=1e-14, max_iters=1, raise_on_fail=False)
+    assert info["status"] == -3 and not info["converged"] and info["iters"] == 1
+    Rbad = R.clone()
+    Rbad[3] = float("nan")
+    with pytest.raises(api.IedgError) as ei:
+        api.gmres_solve(ctx, mesh, K, M, Rbad, restart=5, rtol=1e-10)
+    assert ei.value.status == -4
+    with pytest.raises(api.IedgError):
+        api.gmres_solve(ctx, mesh, K, M, R, restart=0, rtol=1e-10)

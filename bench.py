@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Newton-step solves/s of the IEDG trace solve on one MI355X.
+
+Workload: one subdomain at the paper's shape -- a 16x16x8 structured hex mesh
+with p = 3 (2,048 elements, n = 1,280 local dofs and t = 480 trace dofs per
+element, 6,656 faces of 80 trace dofs, 532,480 trace unknowns), seeded
+synthetic element blocks generated directly in HBM, ten right-hand sides.
+
+A step is one full Newton-step linear solve: condensation of every element,
+assembly of K and R, BILU(0), GMRES(100) and the element back-substitution,
+plus FP64 iterative refinement for the mixed form.  Step k uses right-hand
+side k mod 10.  Both forms are timed at the same tolerance: the relative
+residual of the uncondensed system is <= 1e-8 (FP64 form: GMRES to 1e-8 on
+K; mixed form: FP32 condensation / FP32 K and BILU(0), refined in FP64).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def condense_flops(n, t):
+    # LU of A, U12 = L^{-1} P B, L21 = C U^{-1}, Schur product L21 U12
+    return (2.0 / 3.0) * n ** 3 + 2.0 * n * n * t + 2.0 * n * t * t
+
+
+def cpu_baseline(seed, restart):
+    """The FP64 oracle on a bounded sample, scaled to one full step."""
+    import numpy as np
+    import oracle
+    from synth import StructuredHexMesh, ElementSpec, element_inputs, trace_rhs
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count()
+    from oracle.assembly import matvec
+    sub = StructuredHexMesh(4, 2, 2)
+    spec = ElementSpec(3)
+    blocks = [element_inputs(spec, seed, 0, e) for e in range(sub.n_elem)]
+    G = trace_rhs(spec, seed, 0, sub.n_face)
+    tm = oracle.TraceMesh(sub.elem_faces(), sub.n_face, spec.b)
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        Ks, rs = oracle.condense_all(blocks)
+        t1 = time.perf_counter()
+        K, R = oracle.assemble(tm, Ks, rs, G)
+        fac = oracle.bilu0(tm, K, oracle.greedy_colour_order(tm))
+        uhat, info = oracle.gmres(lambda v: matvec(tm, K, v), lambda v: oracle.bilu0_apply(tm, fac, v), R,
+                                  restart, 1e-8)
+        t2 = time.perf_counter()
+        oracle.backsolve_all(tm, blocks, uhat)
+        t3 = time.perf_counter()
+        runs.append((t1 - t0, t2 - t1, t3 - t2))
+    med = [float(np.median([r[i] for r in runs])) for i in range(3)]
+    full = StructuredHexMesh(16, 16, 8)
+    per_elem = (med[0] + med[2]) / sub.n_elem
+    per_face = med[1] / sub.n_face
+    step_s = per_elem * full.n_elem + per_face * full.n_face
+    work = sum(sum(r) for r in runs)
+    return {"value": 1.0 / step_s, "unit": "Newton-step solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"oracle FP64 solve of a 4x2x2 p=3 mesh with the same distributions ({sub.n_elem} "
+                       f"elements, {sub.n_face} faces, {info['iters']} GMRES iterations), median of 3; element "
+                       f"phases scaled by {full.n_elem}/{sub.n_elem}, trace phases by {full.n_face}/{sub.n_face}; "
+                       f"{work:.1f} s of CPU work"),
+            "condense_elems_per_s": sub.n_elem / med[0]}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dims", default="16,16,8")
+    ap.add_argument("--p", type=int, default=3)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solve is one subdomain on one MI355X; "
+              "multi-GPU runs (RAS across subdomains) are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1605_01020_amd import api, F64, F32
+    from paper_1605_01020_amd.solver import NewtonStepSolver, StepTimer
+    import synth.device as sd
+    from synth import StructuredHexMesh, ElementSpec
+    from synth.matrices import workload
+
+    wl = workload(1)
+    dims = tuple(int(v) for v in args.dims.split(","))
+    spec = ElementSpec(args.p)
+    hmesh = StructuredHexMesh(*dims)
+    E, n, t = hmesh.n_elem, spec.n, spec.t
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b)
+    print(f"[bench] {dims} p={args.p}: E={E} n={n} t={t} faces={hmesh.n_face} nnzb={mesh.nnzb}", file=sys.stderr,
+          flush=True)
+    mats = sd.gen_blocks(spec, wl.seed, 0, E, which="ABCD")
+    n_rhs = wl.n_rhs
+    Fs = [sd.gen_blocks(spec, wl.seed, 0, E, which="F", rhs=k)["F"] for k in range(n_rhs)]
+    Gs = [sd.gen_trace_rhs(spec, wl.seed, 0, hmesh.n_face, rhs=k) for k in range(n_rhs)]
+    torch.cuda.synchronize()
+    print("[bench] inputs generated in HBM", file=sys.stderr, flush=True)
+    A, B, C, D = mats["A"], mats["B"], mats["C"], mats["D"]
+
+    results = {}
+    for form in [f for f in args.forms.split(",") if f]:
+        solver = NewtonStepSolver(ctx, mesh, n, restart=wl.restart)
+        lat, cond_ms, iters, rho, steps_ref = [], [], [], [], []
+
+        def step(k, record):
+            timer = StepTimer(True)
+            F, G = Fs[k % n_rhs], Gs[k % n_rhs]
+            if form == "fp64":
+                z, u, info = solver.solve_fp64(A, B, C, D, F, G, rtol=args.tol, timer=timer)
+            else:
+                z, u, info = solver.solve_mixed(A, B, C, D, F, G, tol=args.tol, prec=F32, timer=timer)
+            if record:
+                cond_ms.append(info["phases_ms"].get("condense", float("nan")))
+                iters.append(info["iters"])
+                steps_ref.append(info.get("refine_steps", 0))
+            return z, u, info
+
+        for k in range(args.warmup):
+            step(k, False)
+        torch.cuda.synchronize()
+        print(f"[bench] {form}: warmup done", file=sys.stderr, flush=True)
+        t_start = time.perf_counter()
+        for k in range(args.steps):
+            t0 = time.perf_counter()
+            z, u, info = step(args.warmup + k, True)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        ctx.sync_status()
+        # accuracy of the last step, outside the timed region
+        k_last = (args.warmup + args.steps - 1) % n_rhs
+        _, _, sums = api.residual_full(ctx, mesh, A, B, C, D, Fs[k_last], Gs[k_last], z, u)
+        s = sums.cpu().numpy()
+        rho_full = math.sqrt((s[0] + s[1]) / (s[2] + s[3]))
+        ms = total * 1e3 / args.steps
+        cms = float(np.mean(cond_ms))
+        results[form] = {"solves_per_s": 1e3 / ms, "ms_per_step": ms,
+                         "elements_condensed_per_s": E / (cms * 1e-3), "condense_ms": cms,
+                         "gmres_iters": iters, "refine_steps": steps_ref, "rho_full": rho_full,
+                         "lat_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                         "phases_ms_last": info["phases_ms"]}
+        print(f"[bench] {form}: {ms:.1f} ms/step, condense {cms:.1f} ms, iters {iters}, rho_full {rho_full:.2e}",
+              file=sys.stderr, flush=True)
+        del solver
+        torch.cuda.empty_cache()
+
+    head = "mixed" if "mixed" in results else "fp64"
+    r = results[head]
+    flops = condense_flops(n, t) * E
+    peak = FP32_PEAK_TFLOPS if head == "mixed" else FP64_PEAK_TFLOPS
+    achieved = flops / (r["condense_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": "Newton-step solves/s at relative residual 1e-8 (mixed FP32/FP64 form; FP64 form beside it)",
+        "value": r["solves_per_s"],
+        "unit": "Newton-step solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic (seeded Philox element blocks generated in HBM)",
+        "config": {"workload": f"IEDG Newton-step trace solve, {dims[0]}x{dims[1]}x{dims[2]} hex mesh, p={args.p}, "
+                               f"E={E}, n={n}, t={t}, N_t={hmesh.n_face * spec.b}, GMRES(100)+BILU(0), 10 RHS",
+                   "form": head, "tol": args.tol},
+        "elements_condensed_per_s": r["elements_condensed_per_s"],
+        "lat_ms": r["lat_ms"],
+        "forms": results,
+        "roofline": {"bound": "mfma", "kernel": "condense", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "flops_per_launch": flops},
+    }
+    if "fp64" in results and "mixed" in results:
+        out["speedup_mixed_vs_fp64"] = results["mixed"]["solves_per_s"] / results["fp64"]["solves_per_s"]
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl.seed, wl.restart)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

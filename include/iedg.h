@@ -113,9 +113,13 @@ iedg_status iedg_mesh_query(iedg_mesh mesh, iedg_mesh_info* info, int32_t* order
  * Inputs (FP64, read only): A [E][n][n], B [E][n][t], C [E][t][n],
  *   D [E][t][t], F [E][n] (F may be NULL: then w and r are not written).
  * Outputs (element type given by prec: double for IEDG_F64, float
- *   otherwise): LU [E][n][n] (unit-lower L below the diagonal, U on and
- *   above), U12 [E][n][t], L21 [E][t][n], Ke [E][t][t]; perm [E][n] int32
- *   (row i of P A is row perm[i] of A); w [E][n] and r [E][t] FP64.
+ *   otherwise): LU [E][n][n], U12 [E][n][t], L21 [E][t][n], Ke [E][t][t];
+ *   perm [E][n] int32 (row i of P A is row perm[i] of A); w [E][n] and
+ *   r [E][t] FP64.  Row interchanges are not applied to the stored rows:
+ *   row i of the packed factors of P A (unit-lower L below the diagonal,
+ *   U on and above) is stored in row perm[i] of LU, and likewise row i of
+ *   U12 and entry i of w sit in row perm[i] (the row of A they came from).
+ *   L21, Ke and r are indexed by the rows of C.
  * Outputs must not overlap inputs.  A zero or non-finite pivot latches
  * IEDG_ERR_SINGULAR with the element index. */
 iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local,
@@ -126,8 +130,9 @@ iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local,
                           double* w, void* Ke, double* r, hipStream_t stream);
 
 /* Right-hand-side-only condensation with retained factors (section 2.2.1):
- * w = L^{-1} P F and r = -L21 w per element.  LU, L21 in `prec`
- * storage as written by iedg_condense. */
+ * w = L^{-1} P F and r = -L21 w per element, w stored in the same row
+ * order as iedg_condense writes it.  LU, perm, L21 as written by
+ * iedg_condense (`prec` storage). */
 iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32_t n_local,
                               int32_t n_trace_elem, iedg_prec prec,
                               const void* LU, const int32_t* perm, const void* L21,
@@ -189,12 +194,13 @@ iedg_status iedg_ilu0_apply(iedg_context ctx, iedg_mesh mesh, iedg_prec mprec,
 
 /* ---- a5: local back-substitution (section 2.2.1) ---------------------- */
 /* z_e = U^{-1} (w_e - U12_e uhat_e) = A_e^{-1} (F_e - B_e uhat_e), where
- * uhat_e gathers the element's t trace dofs from uhat [N_t].  LU, U12 in
- * `prec` storage; w [E][n], uhat, z [E][n] FP64. */
+ * uhat_e gathers the element's t trace dofs from uhat [N_t].  LU, perm,
+ * U12 and w as written by iedg_condense (LU, U12 in `prec` storage); w
+ * [E][n], uhat, z [E][n] FP64, z in the natural order of A's columns. */
 iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, int32_t n_local,
-                                 iedg_prec prec, const void* LU, const void* U12,
-                                 const double* w, const double* uhat, double* z,
-                                 hipStream_t stream);
+                                 iedg_prec prec, const void* LU, const int32_t* perm,
+                                 const void* U12, const double* w, const double* uhat,
+                                 double* z, hipStream_t stream);
 
 /* ---- a6: FP64 residual of the uncondensed system ---------------------- */
 /* rF_e = F_e - A_e z_e - B_e uhat_e,  rG = G - sum_e P_e^T (C_e z_e + D_e uhat_e),

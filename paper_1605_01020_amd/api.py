@@ -61,6 +61,11 @@ class Context:
             err.index = idx.value
             raise err
 
+    def clear_status(self):
+        """Synchronise and discard any latched device-side error."""
+        idx = ctypes.c_int64(-1)
+        self.L.iedg_sync_status(self.h, _stream(), ctypes.byref(idx))
+
     def close(self):
         if self.h:
             self.L.iedg_destroy(self.h)
@@ -199,8 +204,8 @@ def backsolve_local(ctx, mesh, fac, uhat, prec=F64, w=None, z=None):
     w = fac["w"] if w is None else w
     E, n, _ = LU.shape
     z = torch.empty((E, n), dtype=torch.float64, device=uhat.device) if z is None else z
-    ctx.check(ctx.L.iedg_backsolve_local(ctx.h, mesh.h, n, prec, _p(LU), _p(U12), _p(w), _p(uhat),
-                                         _p(z), _stream()))
+    ctx.check(ctx.L.iedg_backsolve_local(ctx.h, mesh.h, n, prec, _p(LU), _p(fac["perm"]), _p(U12), _p(w),
+                                         _p(uhat), _p(z), _stream()))
     return z
 
 

@@ -62,6 +62,17 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Workgroup barrier for data exchanged through GLOBAL memory.  A plain
+// __syncthreads() orders LDS traffic only: it waits for lgkmcnt, not for the
+// wave's outstanding vector-memory stores, and another wave may then read a
+// stale copy.  Drain this wave's vector-memory operations before the barrier
+// and invalidate the CU's vector L1 after it.
+__device__ inline void sync_global() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  asm volatile("buffer_inv sc0" ::: "memory");
+}
+
 // Device status word: first failing index (element or block row) + code.
 struct DeviceStatus {
   int32_t code;   // 0 = ok, otherwise an iedg_status value

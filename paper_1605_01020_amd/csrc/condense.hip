@@ -3,32 +3,38 @@
 // Per element the bordered matrix  M = [A B F; C D 0]  (N = n + t rows,
 // NC = N + 1 columns with F) is reduced by n steps of Gaussian elimination
 // with partial pivoting over the rows of A.  After those steps
-//   rows < n :  unit-lower L and U of P A, U12 = L^{-1} P B, w = L^{-1} P F
-//   rows >= n:  L21 = C U^{-1},  Ke = D - L21 U12,  r = -L21 w
+//   rows of A:  unit-lower L and U of P A, U12 = L^{-1} P B, w = L^{-1} P F
+//   rows of C:  L21 = C U^{-1},  Ke = D - L21 U12,  r = -L21 w
 // so the trailing block is the Schur complement D - C A^{-1} B of eq. LS.
 //
-// Schedule (one 256-thread workgroup per element, 64-wide panels):
+// Row interchanges never move data: pivot position i of P A lives in the
+// physical row perm[i] of every A-row-indexed array (A itself, LU, U12, w),
+// and only the permutation in LDS is updated when a pivot is chosen.
+//
+// Schedule, one 512-thread workgroup (8 waves) per element, 64-wide panels:
 //   for each panel [c0, c1):
-//     1. panel column, Crout order: M[c0:, c0:c1] -= L[c0:, :c0] U[:c0, c0:c1]
-//        (FP64/FP32 MFMA tiles reading the already factored parts)
-//     2. panel factorisation: 8-column leaves held in registers, partial
-//        pivoting over rows c0..n-1 with a workgroup argmax per column,
-//        rows of C finished by a triangular solve with the leaf's U
-//     3. panel row: U[c0:c1, c1:] = L_pp^{-1} (M[c0:c1, c1:] - L[c0:c1,:c0] U[:c0, c1:])
-//   4. Schur block: M[n:, n:] -= L21 U12 (MFMA, K = n)
-// Every entry of M is read from the inputs exactly once, when its tile is
-// first formed; row interchanges of not-yet-read rows are carried by a
-// permutation in LDS, those of already written L rows are applied in place.
+//     1. panel column (Crout order): M[c0:, c0:c1] = in - L[c0:, :c0] U[:c0, c0:c1]
+//        -- MFMA tiles of 256 x 64 fed from double-buffered LDS k-slabs
+//     2. panel factorisation in leaves of 8 columns held in registers:
+//        each leaf first takes the updates of the panel's earlier leaves
+//        (left-looking, fused into its load), then partial pivoting with a
+//        workgroup argmax per column; the panel's L^{-1} is grown in LDS
+//     3. panel row: U[c0:c1, c1:] = L_pp^{-1} (in - L[c0:c1, :c0] U[:c0, c1:])
+//        -- MFMA tiles of 64 x 256; the triangular solve with L_pp^{-1} is a
+//        second MFMA pass on the accumulators (each wave owns whole columns)
+//   4. Schur block: M[n:, n:] = in - L21 U12 (MFMA, K = n)
 #include <climits>
 
 #include "common.h"
 
 namespace iedg {
 
-constexpr int CT = 64;        // Crout tile / panel width
-constexpr int CTP = CT + 1;   // padded LDS row stride
-constexpr int CTHR = 256;     // threads per workgroup (4 waves)
-constexpr int LW = 8;         // leaf width of the panel factorisation
+constexpr int CT = 64;        // panel width
+constexpr int NT = 512;       // threads per workgroup (8 waves)
+constexpr int NW = NT / 64;   // waves
+constexpr int LWT = 8;        // leaf width
+constexpr int KC = 16;        // k-slab depth of the GEMM engine
+constexpr int LIS = CT + 1;   // LDS stride of L^{-1}
 
 template <typename T>
 struct CondenseArgs {
@@ -40,7 +46,8 @@ struct CondenseArgs {
   DeviceStatus* status;
 };
 
-// Addressing of one element's bordered matrix (inputs and outputs).
+// Addressing of one element's bordered matrix.  Rows are pivot positions;
+// a position p < n lives in physical row sperm[p] of A, B, F, LU, U12, w.
 template <typename T>
 struct Elem {
   int n, t, N, NC;
@@ -63,9 +70,10 @@ struct Elem {
   }
   __device__ T ld(int row, int col) const {
     if (row < n) {
-      if (col < n) return LU[(size_t)row * n + col];
-      if (col < N) return U12[(size_t)row * t + (col - n)];
-      return (T)w[row];
+      const size_t pr = (size_t)sperm[row];
+      if (col < n) return LU[pr * n + col];
+      if (col < N) return U12[pr * t + (col - n)];
+      return (T)w[pr];
     }
     const size_t q = (size_t)(row - n);
     if (col < n) return L21[q * n + col];
@@ -74,9 +82,10 @@ struct Elem {
   }
   __device__ void st(int row, int col, T v) const {
     if (row < n) {
-      if (col < n) LU[(size_t)row * n + col] = v;
-      else if (col < N) U12[(size_t)row * t + (col - n)] = v;
-      else w[row] = (double)v;
+      const size_t pr = (size_t)sperm[row];
+      if (col < n) LU[pr * n + col] = v;
+      else if (col < N) U12[pr * t + (col - n)] = v;
+      else w[pr] = (double)v;
       return;
     }
     const size_t q = (size_t)(row - n);
@@ -84,140 +93,268 @@ struct Elem {
     else if (col < N) Ke[q * t + (col - n)] = v;
     else r[q] = (double)v;
   }
-  // row `row` of the L part (columns < n)
+  // L part (columns < n) of position `row`
   __device__ const T* lrow(int row) const {
-    return row < n ? LU + (size_t)row * n : L21 + (size_t)(row - n) * n;
+    return row < n ? LU + (size_t)sperm[row] * n : L21 + (size_t)(row - n) * n;
   }
 };
 
-template <typename T>
-__device__ inline void load4(const T* p, T (&v)[4]);
-template <>
-__device__ inline void load4<double>(const double* p, double (&v)[4]) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
-  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-}
-template <>
-__device__ inline void load4<float>(const float* p, float (&v)[4]) {
-  const float4 a = *reinterpret_cast<const float4*>(p);
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-}
+template <typename T> struct Pair;
+template <> struct Pair<double> { typedef double2 v; };
+template <> struct Pair<float> { typedef float2 v; };
 
-// acc = L[rows, 0:K] * U[0:K, cols] for this wave's 32x32 quadrant of the
-// 64x64 tile at (r0, c0); rows >= rlim and cols >= clim read as zero.
-template <typename T>
-__device__ void tile_gemm(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K,
-                          typename Mfma<T>::acc_t (&acc)[2][2]) {
+// ---- GEMM engine ----------------------------------------------------------
+// acc = L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN tile;
+// rows >= rlim, cols >= clim and k >= K read as zero.  Waves are stacked
+// along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
+// wave 64 x 32).  k-slabs of KC are staged in two LDS buffers; each thread
+// keeps two slabs of global loads in flight.
+template <typename T, int TM, int TN>
+struct Tile {
+  static constexpr int WR = TM >= TN ? NW : 1;
+  static constexpr int WC = NW / WR;
+  static constexpr int WM = TM / WR, WN = TN / WC;
+  static constexpr int RB = WM / 16, CB = WN / 16;
+  static constexpr int SA = TM + 1;   // transposed A slab stride (odd: conflict-free writes)
+  static constexpr int SB = TN + 2;   // B slab stride (keeps pair alignment)
+  static constexpr int STAGE = KC * (SA + SB);
+  static constexpr int AL = TM * KC / 2 / NT;   // pair loads per thread per slab
+  static constexpr int BL = TN * KC / 2 / NT;
+  static_assert(AL >= 1 && BL >= 1 && RB * CB == 8, "tile shape");
+};
+
+template <typename T, int TM, int TN>
+__device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
+                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+  typedef Tile<T, TM, TN> TL;
   typedef Mfma<T> MF;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int rq = r0 + 32 * (wv >> 1), cq = c0 + 32 * (wv & 1);
+  typedef typename Pair<T>::v P2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = MF::zero();
+    for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::zero();
   if (K <= 0) return;
-  const T* arow[2];
-  bool aok[2];
+  const int nch = (K + KC - 1) / KC;
+  // per-thread load slots
+  const T* aptr[TL::AL];
+  int ak[TL::AL], arow[TL::AL];
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb) {
-    const int row = rq + 16 * rb + li;
-    aok[rb] = row < rlim;
-    arow[rb] = el.lrow(aok[rb] ? row : 0);
+  for (int q = 0; q < TL::AL; ++q) {
+    const int idx = tid + q * NT;
+    arow[q] = idx / (KC / 2);
+    ak[q] = 2 * (idx % (KC / 2));
+    const int row = r0 + arow[q];
+    aptr[q] = row < rlim ? el.lrow(row) : nullptr;
   }
-  // B operand: column `col` of the U part (LU upper, U12 or w)
-  const T* bbase[2];
-  const double* wbase[2];
-  int bstride[2];
-  bool bok[2];
+  const T* bbase[TL::BL];
+  const double* bw[TL::BL];
+  int bstride[TL::BL], bk[TL::BL], bcol[TL::BL], bn[TL::BL];
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    const int col = cq + 16 * cb + li;
-    bok[cb] = col < clim;
-    wbase[cb] = nullptr;
-    if (col < el.n) { bbase[cb] = el.LU + col; bstride[cb] = el.n; }
-    else if (col < el.N) { bbase[cb] = el.U12 + (col - el.n); bstride[cb] = el.t; }
-    else { bbase[cb] = el.LU; bstride[cb] = 1; wbase[cb] = el.w; }
+  for (int q = 0; q < TL::BL; ++q) {
+    const int idx = tid + q * NT;
+    bk[q] = idx / (TN / 2);
+    bcol[q] = 2 * (idx % (TN / 2));
+    const int col = c0 + bcol[q];
+    bn[q] = col >= clim ? 0 : (col + 1 >= clim ? 1 : 2);
+    bw[q] = nullptr;
+    bbase[q] = el.LU;
+    bstride[q] = 0;
+    if (col < el.n) { bbase[q] = el.LU + col; bstride[q] = el.n; }
+    else if (col < el.N) { bbase[q] = el.U12 + (col - el.n); bstride[q] = el.t; }
+    else { bw[q] = el.w; }
   }
-  T a[2][4], b[2][4], an[2][4], bn[2][4];
-  auto load = [&](int k0, T (&ao)[2][4], T (&bo)[2][4]) {
-    const int kb = k0 + 4 * lk;
-    const bool full = kb + 3 < K;
+  P2 ra[2][TL::AL], rbv[2][TL::BL];
+  auto gload = [&](int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) {
+    const int k0 = ch * KC;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      if (aok[rb] && full) {
-        load4<T>(arow[rb] + kb, ao[rb]);
-      } else {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) ao[rb][s] = (aok[rb] && kb + s < K) ? arow[rb][kb + s] : T(0);
-      }
+    for (int q = 0; q < TL::AL; ++q) {
+      const int k = k0 + ak[q];
+      P2 v;
+      v.x = T(0); v.y = T(0);
+      if (aptr[q] && k < K) v = *reinterpret_cast<const P2*>(aptr[q] + k);
+      va[q] = v;
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = kb + s;
-        T v = T(0);
-        if (bok[cb] && k < K) v = wbase[cb] ? (T)wbase[cb][k] : bbase[cb][(size_t)k * bstride[cb]];
-        bo[cb][s] = v;
+    for (int q = 0; q < TL::BL; ++q) {
+      const int k = k0 + bk[q];
+      P2 v;
+      v.x = T(0); v.y = T(0);
+      if (k < K && bn[q]) {
+        const size_t pr = (size_t)el.sperm[k];
+        if (bw[q]) {
+          v.x = (T)bw[q][pr];
+        } else if (bn[q] == 2) {
+          v = *reinterpret_cast<const P2*>(bbase[q] + pr * bstride[q]);
+        } else {
+          v.x = bbase[q][pr * bstride[q]];
+        }
       }
+      vb[q] = v;
     }
   };
-  load(0, a, b);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bool more = k0 + 16 < K;
-    if (more) load(k0 + 16, an, bn);
+  auto sstore = [&](int stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) {
+    T* As = smem + stage * TL::STAGE;
+    T* Bs = As + KC * TL::SA;
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = MF::mac(a[rb][s], b[cb][s], acc[rb][cb]);
-    if (more) {
-#pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) { a[rb][s] = an[rb][s]; b[rb][s] = bn[rb][s]; }
+    for (int q = 0; q < TL::AL; ++q) {
+      As[ak[q] * TL::SA + arow[q]] = va[q].x;
+      As[(ak[q] + 1) * TL::SA + arow[q]] = va[q].y;
     }
+#pragma unroll
+    for (int q = 0; q < TL::BL; ++q) *reinterpret_cast<P2*>(Bs + bk[q] * TL::SB + bcol[q]) = vb[q];
+  };
+  gload(0, ra[0], rbv[0]);
+  if (nch > 1) gload(1, ra[1], rbv[1]);
+  sstore(0, ra[0], rbv[0]);
+  if (nch > 2) gload(2, ra[0], rbv[0]);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int nxt = ch + 1;
+    if (nxt < nch) {
+      if (nxt & 1) sstore(1, ra[1], rbv[1]); else sstore(0, ra[0], rbv[0]);
+      if (nxt + 2 < nch) {
+        if (nxt & 1) gload(nxt + 2, ra[1], rbv[1]); else gload(nxt + 2, ra[0], rbv[0]);
+      }
+    }
+    const T* As = smem + (ch & 1) * TL::STAGE;
+    const T* Bs = As + KC * TL::SA;
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      T av[TL::RB], bv[TL::CB];
+#pragma unroll
+      for (int rb = 0; rb < TL::RB; ++rb) av[rb] = As[(4 * ks + lg) * TL::SA + wr0 + 16 * rb + li];
+#pragma unroll
+      for (int cb = 0; cb < TL::CB; ++cb) bv[cb] = Bs[(4 * ks + lg) * TL::SB + wc0 + 16 * cb + li];
+#pragma unroll
+      for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
+    }
+    __syncthreads();
   }
 }
 
-// For each accumulator element of this wave: (row, col) inside the tile.
-template <typename T, typename F>
-__device__ inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[2][2], F f) {
+// Visit this wave's accumulator elements as (row, col) of the tile.
+template <typename T, int TM, int TN, typename F>
+__device__ inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                               F f) {
+  typedef Tile<T, TM, TN> TL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int rq = r0 + 32 * (wv >> 1), cq = c0 + 32 * (wv & 1);
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < TL::CB; ++cb)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        f(rq + 16 * rb + Mfma<T>::row(lane, v), cq + 16 * cb + (lane & 15), acc[rb][cb][v]);
+        f(r0 + wr0 + 16 * rb + Mfma<T>::row(lane, v), c0 + wc0 + 16 * cb + (lane & 15), acc[rb][cb][v]);
 }
 
-struct LeafSmem {
-  double red_v[4];
-  int red_i[4];
-  int swaps[LW];
+// acc element v = f(row, col, value) over this wave's accumulators.
+template <typename T, int TM, int TN, typename F>
+__device__ inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                               F f) {
+  typedef Tile<T, TM, TN> TL;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
+#pragma unroll
+  for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < TL::CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc[rb][cb][v] = f(r0 + wr0 + 16 * rb + Mfma<T>::row(lane, v), c0 + wc0 + 16 * cb + (lane & 15), acc[rb][cb][v]);
+}
+
+// ---- panel factorisation -------------------------------------------------
+struct PanelSmem {
+  double red_v[NW];
+  int red_i[NW];
+  int piv;
 };
 
-// Factor panel columns [c0, c1) (already Crout-updated) in leaves of LW.
-template <typename T, int QMAX, int QCMAX, int LWT>
-__device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, T* sprow, T* skrow,
-                             T* suleaf, T* slleaf, T* sU, LeafSmem* ls, DeviceStatus* status, int elem) {
+template <typename T>
+struct PanelBufs {
+  T* Linv;   // CT x LIS: L_pp^{-1} of the panel's factored columns so far
+  T* Xu;     // CT x LWT: rows [c0, cs) of the leaf columns (input / U)
+  T* Lb;     // LWT x CT: L(cs:ce, c0:ce) rows of the leaf
+  T* prow;   // LWT: pivot row of the current column
+  T* krow;   // LWT
+  T* ul;     // LWT x LWT: U of the leaf's diagonal block
+  PanelSmem* ps;
+};
+
+template <typename T, int QA, int QC>
+__device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, const PanelBufs<T>& pb,
+                             DeviceStatus* status, int elem) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = el.n, N = el.N;
   for (int cs = c0; cs < c1; cs += LWT) {
-    const int ce = min(cs + LWT, c1), lw = ce - cs;
-    T x[QMAX][LWT];
-#pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int row = cs + tid + CTHR * q;
-#pragma unroll
-      for (int j = 0; j < LWT; ++j) x[q][j] = (row < n && j < lw) ? el.ld(row, cs + j) : T(0);
+    const int ce = min(cs + LWT, c1), lw = ce - cs, kp = cs - c0;  // kp: panel columns already factored
+    // (a) U rows [c0, cs) of the leaf columns: U = Linv[0:kp, 0:kp] X
+    if (kp > 0) {
+      for (int q = tid; q < kp * LWT; q += NT) {
+        const int i = q / LWT, j = q % LWT;
+        pb.Xu[i * LWT + j] = j < lw ? el.ld(c0 + i, cs + j) : T(0);
+      }
+      __syncthreads();
+      T u_val = T(0);
+      int ui = -1, uj = 0;
+      if (tid < kp * LWT) {
+        ui = tid / LWT;
+        uj = tid % LWT;
+        T s = T(0);
+        for (int k = 0; k <= ui; ++k) s += pb.Linv[ui * LIS + k] * pb.Xu[k * LWT + uj];
+        u_val = s;
+      }
+      __syncthreads();
+      if (ui >= 0) {
+        pb.Xu[ui * LWT + uj] = u_val;
+        if (uj < lw) el.st(c0 + ui, cs + uj, u_val);
+      }
+      sync_global();
     }
+    // (b) load the leaf rows with the panel's earlier updates applied
+    T x[QA][LWT];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int row = cs + tid + NT * q;
+#pragma unroll
+      for (int j = 0; j < LWT; ++j) x[q][j] = T(0);
+      if (row < n) {
+#pragma unroll
+        for (int j = 0; j < LWT; ++j)
+          if (j < lw) x[q][j] = el.ld(row, cs + j);
+        const T* lr = el.lrow(row) + c0;
+        for (int k = 0; k < kp; ++k) {
+          const T l = lr[k];
+#pragma unroll
+          for (int j = 0; j < LWT; ++j) x[q][j] -= l * pb.Xu[k * LWT + j];
+        }
+      }
+    }
+    T xc[QC][LWT];
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const int row = n + tid + NT * q;
+#pragma unroll
+      for (int j = 0; j < LWT; ++j) xc[q][j] = T(0);
+      if (row < N) {
+#pragma unroll
+        for (int j = 0; j < LWT; ++j)
+          if (j < lw) xc[q][j] = el.ld(row, cs + j);
+        const T* lr = el.lrow(row) + c0;
+        for (int k = 0; k < kp; ++k) {
+          const T l = lr[k];
+#pragma unroll
+          for (int j = 0; j < LWT; ++j) xc[q][j] -= l * pb.Xu[k * LWT + j];
+        }
+      }
+    }
+    // (c) partial pivoting over positions [k, n), one column at a time
 #pragma unroll
     for (int kk = 0; kk < LWT; ++kk) {
       if (kk < lw) {
@@ -225,10 +362,10 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, T* s
         double best = -1.0;
         int bidx = INT_MAX;
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-          const int row = cs + tid + CTHR * q;
+        for (int q = 0; q < QA; ++q) {
+          const int row = cs + tid + NT * q;
           const double v = fabs((double)x[q][kk]);
-          if (row >= k && row < n && (v > best)) { best = v; bidx = row; }
+          if (row >= k && row < n && v > best) { best = v; bidx = row; }
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -236,14 +373,14 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, T* s
           const int oi = __shfl_xor(bidx, off, kWave);
           if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
-        if (lane == 0) { ls->red_v[wv] = best; ls->red_i[wv] = bidx; }
+        if (lane == 0) { pb.ps->red_v[wv] = best; pb.ps->red_i[wv] = bidx; }
         __syncthreads();
-        best = ls->red_v[0];
-        bidx = ls->red_i[0];
+        best = pb.ps->red_v[0];
+        bidx = pb.ps->red_i[0];
 #pragma unroll
-        for (int i = 1; i < 4; ++i) {
-          const double ov = ls->red_v[i];
-          const int oi = ls->red_i[i];
+        for (int i = 1; i < NW; ++i) {
+          const double ov = pb.ps->red_v[i];
+          const int oi = pb.ps->red_i[i];
           if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
         int piv = bidx;
@@ -251,44 +388,43 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, T* s
           if (tid == 0) latch_status(status, IEDG_ERR_SINGULAR, elem);
           piv = k;
         }
-        const int po = piv - cs;  // owner of the pivot row: tid po % CTHR, slot po / CTHR
-        if (tid == (po % CTHR)) {
+        const int po = piv - cs;  // owner: thread po % NT, slot po / NT
+        if (tid == po % NT) {
 #pragma unroll
-          for (int q = 0; q < QMAX; ++q)
-            if (q == po / CTHR)
+          for (int q = 0; q < QA; ++q)
+            if (q == po / NT)
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) sprow[j] = x[q][j];
+              for (int j = 0; j < LWT; ++j) pb.prow[j] = x[q][j];
         }
         if (tid == kk) {
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) skrow[j] = x[0][j];
+          for (int j = 0; j < LWT; ++j) pb.krow[j] = x[0][j];
         }
         __syncthreads();
-        if (piv != k && tid == (po % CTHR)) {
+        if (piv != k && tid == po % NT) {
 #pragma unroll
-          for (int q = 0; q < QMAX; ++q)
-            if (q == po / CTHR)
+          for (int q = 0; q < QA; ++q)
+            if (q == po / NT)
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) x[q][j] = skrow[j];
+              for (int j = 0; j < LWT; ++j) x[q][j] = pb.krow[j];
         }
         if (tid == kk) {
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) x[0][j] = sprow[j];
+          for (int j = 0; j < LWT; ++j) x[0][j] = pb.prow[j];
         }
         if (tid == 0) {
           const int tmp = sperm[k];
           sperm[k] = sperm[piv];
           sperm[piv] = tmp;
-          ls->swaps[kk] = piv;
         }
-        if (tid < LWT) suleaf[kk * LW + tid] = sprow[tid];
-        const T ukk = sprow[kk];
+        if (tid < LWT) pb.ul[kk * LWT + tid] = pb.prow[tid];
         T u[LWT];
 #pragma unroll
-        for (int j = 0; j < LWT; ++j) u[j] = sprow[j];
+        for (int j = 0; j < LWT; ++j) u[j] = pb.prow[j];
+        const T ukk = u[kk];
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-          const int row = cs + tid + CTHR * q;
+        for (int q = 0; q < QA; ++q) {
+          const int row = cs + tid + NT * q;
           if (row > k && row < n) {
             const T l = x[q][kk] / ukk;
             x[q][kk] = l;
@@ -296,129 +432,110 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, T* s
             for (int j = kk + 1; j < LWT; ++j) x[q][j] -= l * u[j];
           }
         }
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+          if (n + tid + NT * q < N) {
+            const T l = xc[q][kk] / ukk;
+            xc[q][kk] = l;
+#pragma unroll
+            for (int j = kk + 1; j < LWT; ++j) xc[q][j] -= l * u[j];
+          }
+        }
         __syncthreads();
       }
     }
-    // write the leaf back (rows of A) and record L of the leaf's own rows
+    // (d) write the leaf back (positions now final for rows [cs, ce))
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
-      const int row = cs + tid + CTHR * q;
+    for (int q = 0; q < QA; ++q) {
+      const int row = cs + tid + NT * q;
       if (row < n)
 #pragma unroll
         for (int j = 0; j < LWT; ++j)
           if (j < lw) el.st(row, cs + j, x[q][j]);
     }
+#pragma unroll
+    for (int q = 0; q < QC; ++q) {
+      const int row = n + tid + NT * q;
+      if (row < N)
+#pragma unroll
+        for (int j = 0; j < LWT; ++j)
+          if (j < lw) el.st(row, cs + j, xc[q][j]);
+    }
+    // leaf rows' own L (diagonal block, unit lower) into Lb[:, kp:kp+lw]
     if (tid < lw) {
 #pragma unroll
-      for (int j = 0; j < LWT; ++j) slleaf[tid * LW + j] = (j < tid) ? x[0][j] : T(0);
+      for (int j = 0; j < LWT; ++j) pb.Lb[tid * CT + kp + j] = (j < tid) ? x[0][j] : T(0);
     }
-    // rows of C: L21 = X U_leaf^{-1}
-    T xc[QCMAX][LWT];
-#pragma unroll
-    for (int q = 0; q < QCMAX; ++q) {
-      const int row = n + tid + CTHR * q;
-      const bool ok = row < N;
-#pragma unroll
-      for (int j = 0; j < LWT; ++j) xc[q][j] = (ok && j < lw) ? el.ld(row, cs + j) : T(0);
-      if (ok) {
-#pragma unroll
-        for (int j = 0; j < LWT; ++j) {
-          if (j < lw) {
-            T v = xc[q][j];
-#pragma unroll
-            for (int k2 = 0; k2 < j; ++k2) v -= xc[q][k2] * suleaf[k2 * LW + j];
-            xc[q][j] = v / suleaf[j * LW + j];
-            el.st(row, cs + j, xc[q][j]);
-          }
-        }
-      }
-    }
-    // apply this leaf's interchanges to the columns outside the leaf that
-    // hold already-formed values: [0, cs) (L) and [ce, c1) (panel remainder)
-    {
-      const int nother = cs + (c1 - ce);
-      for (int m = tid; m < nother; m += CTHR) {
-        const int col = m < cs ? m : ce + (m - cs);
-        for (int kk = 0; kk < lw; ++kk) {
-          const int p = ls->swaps[kk];
-          const int k = cs + kk;
-          if (p != k) {
-            const T a = el.ld(k, col), b2 = el.ld(p, col);
-            el.st(k, col, b2);
-            el.st(p, col, a);
-          }
-        }
-      }
+    sync_global();
+    // leaf rows' L in the panel's earlier columns: Lb[:, 0:kp]
+    for (int q = tid; q < lw * kp; q += NT) {
+      const int i = q / kp, k = q % kp;
+      pb.Lb[i * CT + k] = el.ld(cs + i, c0 + k);
     }
     __syncthreads();
-    const int nright = c1 - ce;
-    if (nright > 0) {
-      // (i) rows [cs, ce) of the remaining panel columns: U = L_leaf^{-1} X
-      if (tid < nright) {
-        const int col = ce + tid;
-        T v[LWT];
-#pragma unroll
-        for (int i = 0; i < LWT; ++i) {
-          if (i < lw) {
-            T s = el.ld(cs + i, col);
-#pragma unroll
-            for (int k2 = 0; k2 < i; ++k2) s -= slleaf[i * LW + k2] * v[k2];
-            v[i] = s;
-            el.st(cs + i, col, s);
-            sU[i * CT + tid] = s;
-          } else {
-            v[i] = T(0);
-            sU[i * CT + tid] = T(0);
-          }
-        }
+    // (e) grow L_pp^{-1}: rows kp..kp+lw.  With L = [L11 0; L21 L22]:
+    //     inv = [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}]
+    //     first  Y = L21 L11^{-1}  (lw x kp), then rows = -L22^{-1} Y and L22^{-1}
+    {
+      T* Y = pb.Xu;  // reuse: lw x kp values, stored as Y[i * CT + k] (fits: LWT*CT <= CT*LWT)
+      for (int q = tid; q < lw * kp; q += NT) {
+        const int i = q / kp, k = q % kp;
+        T s = T(0);
+        for (int m = k; m < kp; ++m) s += pb.Lb[i * CT + m] * pb.Linv[m * LIS + k];
+        Y[i * CT + k] = s;
       }
       __syncthreads();
-      // (ii) rank-lw update of rows [ce, N) in the remaining panel columns
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const int row = cs + tid + CTHR * q;
-        if (row >= ce && row < n) {
-          for (int j = 0; j < nright; ++j) {
-            T s = el.ld(row, ce + j);
-#pragma unroll
-            for (int k2 = 0; k2 < LWT; ++k2) s -= x[q][k2] * sU[k2 * CT + j];
-            el.st(row, ce + j, s);
-          }
+      // L22^{-1} (unit lower lw x lw) by forward substitution, one thread per column
+      // then the new block row; done by threads (i, k) in sequence of i
+      if (tid < lw) {
+        const int j = tid;
+        for (int i = 0; i < lw; ++i) {
+          T s = (i == j) ? T(1) : T(0);
+          if (i > j)
+            for (int m = j; m < i; ++m) s -= pb.Lb[i * CT + kp + m] * pb.Linv[(kp + m) * LIS + kp + j];
+          pb.Linv[(kp + i) * LIS + kp + j] = s;
         }
+        for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * LIS + kp + j] = T(0);
       }
-#pragma unroll
-      for (int q = 0; q < QCMAX; ++q) {
-        const int row = n + tid + CTHR * q;
-        if (row < N) {
-          for (int j = 0; j < nright; ++j) {
-            T s = el.ld(row, ce + j);
-#pragma unroll
-            for (int k2 = 0; k2 < LWT; ++k2) s -= xc[q][k2] * sU[k2 * CT + j];
-            el.st(row, ce + j, s);
-          }
-        }
+      __syncthreads();
+      for (int q = tid; q < lw * kp; q += NT) {
+        const int i = q / kp, k = q % kp;
+        T s = T(0);
+        for (int m = 0; m <= i; ++m) s += pb.Linv[(kp + i) * LIS + kp + m] * Y[m * CT + k];
+        pb.Linv[(kp + i) * LIS + k] = -s;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
-template <typename T, int QMAX, int QCMAX, int LWT>
-__global__ __launch_bounds__(CTHR) void condense_kernel(CondenseArgs<T> a) {
+// ---- the kernel -------------------------------------------------------------
+template <typename T>
+struct CondenseSmem {
+  static constexpr int GEMM = 2 * (KC * (256 + 1 + 64 + 2));   // elements, both tile shapes
+  static size_t bytes(int n) {
+    return sizeof(T) * (GEMM + CT * LIS + CT * LWT + LWT * CT + 2 * LWT + LWT * LWT) + sizeof(PanelSmem) + 16 +
+           sizeof(int) * n;
+  }
+};
+
+template <typename T, int QA, int QC>
+__global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   typedef Mfma<T> MF;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
   const int n = a.n, t = a.t, N = n + t;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sLinv = reinterpret_cast<T*>(smem_raw);          // CT x CTP
-  T* sX = sLinv + CT * CTP;                           // CT x CTP
-  T* sprow = sX + CT * CTP;                           // LW
-  T* skrow = sprow + LW;                              // LW
-  T* suleaf = skrow + LW;                             // LW x LW
-  T* slleaf = suleaf + LW * LW;                       // LW x LW
-  T* sU = slleaf + LW * LW;                           // LW x CT
-  LeafSmem* ls = reinterpret_cast<LeafSmem*>(sU + LW * CT);
-  int* sperm = reinterpret_cast<int*>(ls + 1);        // n
+  T* sg = reinterpret_cast<T*>(smem_raw);
+  PanelBufs<T> pb;
+  pb.Linv = sg + CondenseSmem<T>::GEMM;
+  pb.Xu = pb.Linv + CT * LIS;
+  pb.Lb = pb.Xu + CT * LWT;
+  pb.prow = pb.Lb + LWT * CT;
+  pb.krow = pb.prow + LWT;
+  pb.ul = pb.krow + LWT;
+  pb.ps = reinterpret_cast<PanelSmem*>(pb.ul + LWT * LWT);
+  int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
 
   Elem<T> el;
   el.n = n; el.t = t; el.N = N; el.NC = a.F ? N + 1 : N;
@@ -431,115 +548,103 @@ __global__ __launch_bounds__(CTHR) void condense_kernel(CondenseArgs<T> a) {
   el.sperm = sperm;
   const int NC = el.NC;
 
-  for (int i = tid; i < n; i += CTHR) sperm[i] = i;
+  for (int i = tid; i < n; i += NT) sperm[i] = i;
   __syncthreads();
 
-  typename MF::acc_t acc[2][2];
+  typedef Tile<T, 256, 64> TA;
+  typedef Tile<T, 64, 256> TB;
   for (int c0 = 0; c0 < n; c0 += CT) {
     const int c1 = min(c0 + CT, n);
     // 1. panel column in Crout order
-    for (int r0 = c0; r0 < N; r0 += CT) {
-      tile_gemm<T>(el, r0, N, c0, c1, c0, acc);
-      for_acc<T>(r0, c0, acc, [&](int row, int col, T v) {
+    for (int r0 = c0; r0 < N; r0 += 256) {
+      typename MF::acc_t acc[TA::RB][TA::CB];
+      gemm_tile<T, 256, 64>(el, r0, N, c0, c1, c0, sg, acc);
+      for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) {
         if (row < N && col < c1) el.st(row, col, el.in(row, col) - v);
       });
     }
-    __syncthreads();
-    // 2. factor the panel
-    panel_factor<T, QMAX, QCMAX, LWT>(el, sperm, c0, c1, sprow, skrow, suleaf, slleaf, sU, ls, a.status, e);
-    // 3a. L_pp^{-1} (unit lower, zero padded) into sLinv
+    sync_global();
+    // 2. factor the panel, growing L_pp^{-1}
+    panel_factor<T, QA, QC>(el, sperm, c0, c1, pb, a.status, e);
+    // the leaves write L_pp^{-1} on and below the diagonal of each 8-row
+    // strip only; the triangular solve below reads whole 16 x 16 diagonal
+    // blocks, so clear the strictly upper part (and the padding of a
+    // narrow last panel)
     const int wp = c1 - c0;
-    for (int i = tid; i < CT * CT; i += CTHR) {
-      const int r = i / CT, c = i % CT;
-      sX[r * CTP + c] = (r < wp && c < r) ? el.ld(c0 + r, c0 + c) : T(0);
+    for (int q = tid; q < CT * CT; q += NT) {
+      const int i = q / CT, k = q % CT;
+      if (i >= wp || k >= wp || k > i) pb.Linv[i * LIS + k] = T(0);
     }
     __syncthreads();
-    if (tid < CT) {
-      const int j = tid;
-      for (int i = 0; i < CT; ++i) {
-        T s = (i == j) ? T(1) : T(0);
-        if (i > j && i < wp) {
-          for (int k = j; k < i; ++k) s -= sX[i * CTP + k] * sLinv[k * CTP + j];
-        }
-        sLinv[i * CTP + j] = (i < wp && j < wp) ? s : T(0);
-      }
-    }
-    __syncthreads();
-    // 3b. panel row: U[c0:c1, c1:NC]
-    for (int j0 = c1; j0 < NC; j0 += CT) {
-      const int jl = min(j0 + CT, NC);
-      tile_gemm<T>(el, c0, c1, j0, jl, c0, acc);
-      for_acc<T>(c0, j0, acc, [&](int row, int col, T v) {
-        sX[(row - c0) * CTP + (col - j0)] = (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
+    // 3. panel row with the triangular solve on the accumulators
+    for (int j0 = c1; j0 < NC; j0 += 256) {
+      const int jl = min(j0 + 256, NC);
+      typename MF::acc_t acc[TB::RB][TB::CB];
+      gemm_tile<T, 64, 256>(el, c0, c1, j0, jl, c0, sg, acc);
+      map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) -> T {
+        return (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
       });
-      __syncthreads();
-      // acc = Linv (64x64) * X (64x64) from LDS
       {
-        const int lane = tid & 63, wv = tid >> 6;
-        const int li = lane & 15, lk = lane >> 4;
-        const int rq = 32 * (wv >> 1), cq = 32 * (wv & 1);
+        const int lane = tid & 63, li = lane & 15;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int ib = TB::RB - 1; ib >= 0; --ib) {
+          typename MF::acc_t nacc[TB::CB];
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = MF::zero();
-        for (int k0 = 0; k0 < wp; k0 += 4) {
-          T av[2], bv[2];
+          for (int cb = 0; cb < TB::CB; ++cb) nacc[cb] = MF::zero();
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb) av[rb] = sLinv[(rq + 16 * rb + li) * CTP + k0 + lk];
+          for (int rb = 0; rb <= ib; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) bv[cb] = sX[(k0 + lk) * CTP + cq + 16 * cb + li];
+            for (int v = 0; v < 4; ++v) {
+              const T av = pb.Linv[(16 * ib + li) * LIS + 16 * rb + MF::row(lane, v)];
 #pragma unroll
-          for (int rb = 0; rb < 2; ++rb)
+              for (int cb = 0; cb < TB::CB; ++cb) nacc[cb] = MF::mac(av, acc[rb][cb][v], nacc[cb]);
+            }
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
+          for (int cb = 0; cb < TB::CB; ++cb) acc[ib][cb] = nacc[cb];
         }
       }
-      for_acc<T>(c0, j0, acc, [&](int row, int col, T v) {
+      for_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) {
         if (row < c1 && col < jl) el.st(row, col, v);
       });
-      __syncthreads();
     }
-    __syncthreads();
+    sync_global();
   }
   // 4. Schur block
-  for (int r0 = n; r0 < N; r0 += CT) {
-    for (int j0 = n; j0 < NC; j0 += CT) {
-      const int jl = min(j0 + CT, NC);
-      tile_gemm<T>(el, r0, N, j0, jl, n, acc);
-      for_acc<T>(r0, j0, acc, [&](int row, int col, T v) {
+  for (int r0 = n; r0 < N; r0 += 256) {
+    for (int j0 = n; j0 < NC; j0 += 64) {
+      const int jl = min(j0 + 64, NC);
+      typename MF::acc_t acc[TA::RB][TA::CB];
+      gemm_tile<T, 256, 64>(el, r0, N, j0, jl, n, sg, acc);
+      for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) {
         if (row < N && col < jl) el.st(row, col, el.in(row, col) - v);
       });
     }
   }
-  for (int i = tid; i < n; i += CTHR) a.perm[(size_t)e * n + i] = sperm[i];
+  for (int i = tid; i < n; i += NT) a.perm[(size_t)e * n + i] = sperm[i];
 }
 
-template <typename T>
-static size_t condense_smem(int n) {
-  return sizeof(T) * (2 * CT * CTP + 2 * LW + 2 * LW * LW + LW * CT) + sizeof(LeafSmem) + sizeof(int) * n;
-}
-
-template <typename T, int QMAX, int QCMAX, int LWT>
+template <typename T, int QA, int QC>
 static hipError_t launch_condense(const CondenseArgs<T>& a, hipStream_t s) {
-  const size_t smem = condense_smem<T>(a.n);
-  auto kern = condense_kernel<T, QMAX, QCMAX, LWT>;
+  const size_t smem = CondenseSmem<T>::bytes(a.n);
+  auto kern = condense_kernel<T, QA, QC>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.E), dim3(CTHR), smem, s, a);
+  hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s) {
-  const int qa = (a.n + CTHR - 1) / CTHR, qc = (a.t + CTHR - 1) / CTHR;
-  if (qa <= 3 && qc <= 2) return launch_condense<T, 3, 2, 8>(a, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, 8>(a, s);
-  if (qa <= 10 && qc <= 3) return launch_condense<T, 10, 3, 4>(a, s);
+  const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, s);
   return hipErrorInvalidValue;
 }
 
 // ---- right-hand side condensation: w = L^{-1} P F, r = -L21 w ----------
+// Position i of P A is physical row perm[i] of LU and of w.
 constexpr int RTHR = 256;
 
 template <typename T>
@@ -550,24 +655,27 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* y = reinterpret_cast<double*>(smem_raw);  // n
   double* blk = y + n;                              // 64 x 65
+  int* sp = reinterpret_cast<int*>(blk + 64 * 65);  // n
   const T* L = LU + (size_t)e * n * n;
   const int32_t* p = perm + (size_t)e * n;
   const double* f = F + (size_t)e * n;
-  for (int i = tid; i < n; i += RTHR) y[i] = f[p[i]];
+  for (int i = tid; i < n; i += RTHR) {
+    sp[i] = p[i];
+    y[i] = f[p[i]];
+  }
   __syncthreads();
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int i1 = min(i0 + 64, n), bw = i1 - i0;
-    // y[i0:i1] -= L[i0:i1, 0:i0] y[0:i0]   (one wave per row)
     for (int i = i0 + wv; i < i1; i += RTHR / 64) {
       double s = 0.0;
-      const T* row = L + (size_t)i * n;
+      const T* row = L + (size_t)sp[i] * n;
       for (int k = lane; k < i0; k += 64) s += (double)row[k] * y[k];
       s = wave_sum(s);
       if (lane == 0) y[i] -= s;
     }
     for (int q = tid; q < 64 * 64; q += RTHR) {
       const int rr = q / 64, cc = q % 64;
-      blk[rr * 65 + cc] = (rr < bw && cc < rr) ? (double)L[(size_t)(i0 + rr) * n + i0 + cc] : 0.0;
+      blk[rr * 65 + cc] = (rr < bw && cc < rr) ? (double)L[(size_t)sp[i0 + rr] * n + i0 + cc] : 0.0;
     }
     __syncthreads();
     if (wv == 0) {
@@ -580,7 +688,7 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += RTHR) w[(size_t)e * n + i] = y[i];
+  for (int i = tid; i < n; i += RTHR) w[(size_t)e * n + sp[i]] = y[i];
   const T* L2 = L21 + (size_t)e * t * n;
   for (int i = wv; i < t; i += RTHR / 64) {
     double s = 0.0;
@@ -608,7 +716,7 @@ extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n
   if (F && (!w || !r)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense: F given without w and r");
   if ((n_local & 3) || (n_trace_elem & 1))
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: n must be a multiple of 4, t even");
-  if (n_local > 10 * CTHR || n_trace_elem > 3 * CTHR)
+  if (n_local > 5 * NT || n_trace_elem > 2 * NT)
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: n=%d t=%d too large", n_local, n_trace_elem);
   hipError_t err;
   if (prec == IEDG_F64) {
@@ -634,7 +742,7 @@ extern "C" iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense_rhs: bad sizes");
   if (n_elem == 0) return IEDG_OK;
   if (!LU || !perm || !L21 || !F || !w || !r) return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense_rhs: null pointer");
-  const size_t smem = sizeof(double) * (n_local + 64 * 65);
+  const size_t smem = sizeof(double) * (n_local + 64 * 65) + sizeof(int) * n_local;
   if (prec == IEDG_F64) {
     auto k = condense_rhs_kernel<double>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));

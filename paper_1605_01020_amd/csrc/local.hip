@@ -8,28 +8,31 @@ namespace iedg {
 constexpr int LTHR = 256;
 constexpr int LWAVES = LTHR / 64;
 
-// z_e = U^{-1} (w_e - U12_e uhat_e): one workgroup per element.
+// z_e = U^{-1} (w_e - U12_e uhat_e): one workgroup per element.  Position i
+// of the factorisation lives in physical row perm[i] of LU, U12 and w.
 template <typename T>
 __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, const int32_t* elem_faces, const T* LU,
-                                                         const T* U12, const double* w, const double* uhat,
-                                                         double* z) {
+                                                         const int32_t* perm, const T* U12, const double* w,
+                                                         const double* uhat, double* z) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ue = reinterpret_cast<double*>(smem_raw);  // t
   double* y = ue + t;                                // n
   double* blk = y + n;                               // 64 x 65
+  int* sp = reinterpret_cast<int*>(blk + 64 * 65);   // n
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < t; i += LTHR) {
     const int a = i / b, l = i % b;
     ue[i] = uhat[(size_t)elem_faces[6 * e + a] * b + l];
   }
+  for (int i = tid; i < n; i += LTHR) sp[i] = perm[(size_t)e * n + i];
   __syncthreads();
   const T* U12e = U12 + (size_t)e * n * t;
   for (int i = wv; i < n; i += LWAVES) {
-    const T* row = U12e + (size_t)i * t;
+    const T* row = U12e + (size_t)sp[i] * t;
     double s = 0.0;
     for (int k = lane; k < t; k += 64) s += (double)row[k] * ue[k];
     s = wave_sum(s);
-    if (lane == 0) y[i] = w[(size_t)e * n + i] - s;
+    if (lane == 0) y[i] = w[(size_t)e * n + sp[i]] - s;
   }
   __syncthreads();
   const T* U = LU + (size_t)e * n * n;
@@ -38,7 +41,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
     const int i0 = bi * 64, i1 = min(i0 + 64, n), bw = i1 - i0;
     // y[i0:i1] -= U[i0:i1, i1:n] z[i1:n]   (z stored in y beyond i1)
     for (int i = i0 + wv; i < i1; i += LWAVES) {
-      const T* row = U + (size_t)i * n;
+      const T* row = U + (size_t)sp[i] * n;
       double s = 0.0;
       for (int k = i1 + lane; k < n; k += 64) s += (double)row[k] * y[k];
       s = wave_sum(s);
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
     }
     for (int q = tid; q < 64 * 64; q += LTHR) {
       const int rr = q / 64, cc = q % 64;
-      blk[rr * 65 + cc] = (rr < bw && cc < bw && cc >= rr) ? (double)U[(size_t)(i0 + rr) * n + i0 + cc] : 0.0;
+      blk[rr * 65 + cc] = (rr < bw && cc < bw && cc >= rr) ? (double)U[(size_t)sp[i0 + rr] * n + i0 + cc] : 0.0;
     }
     __syncthreads();
     if (wv == 0) {
@@ -165,21 +168,21 @@ __global__ void sum4_kernel(const double* p0, int64_t n0, const double* p1, int6
 using namespace iedg;
 
 extern "C" iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, int32_t n_local, iedg_prec prec,
-                                            const void* LU, const void* U12, const double* w, const double* uhat,
-                                            double* z, hipStream_t stream) {
-  if (!ctx || !mesh || !LU || !U12 || !w || !uhat || !z || n_local <= 0) return IEDG_ERR_INVALID_ARG;
+                                            const void* LU, const int32_t* perm, const void* U12, const double* w,
+                                            const double* uhat, double* z, hipStream_t stream) {
+  if (!ctx || !mesh || !LU || !perm || !U12 || !w || !uhat || !z || n_local <= 0) return IEDG_ERR_INVALID_ARG;
   const int n = n_local, t = mesh->t, b = mesh->b;
-  const size_t smem = sizeof(double) * (t + n + 64 * 65);
+  const size_t smem = sizeof(double) * (t + n + 64 * 65) + sizeof(int) * n;
   if (prec == IEDG_F64) {
     auto k = backsolve_kernel<double>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
-                       (const double*)LU, (const double*)U12, w, uhat, z);
+                       (const double*)LU, perm, (const double*)U12, w, uhat, z);
   } else {
     auto k = backsolve_kernel<float>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
-                       (const float*)LU, (const float*)U12, w, uhat, z);
+                       (const float*)LU, perm, (const float*)U12, w, uhat, z);
   }
   IEDG_LAUNCH_CHECK(ctx, "backsolve launch");
   return IEDG_OK;

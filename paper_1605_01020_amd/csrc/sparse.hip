@@ -267,12 +267,12 @@ __global__ __launch_bounds__(STHR) void ilu0_level_kernel(int b, const int32_t* 
     const int sik = lslot[2 * l], dk = lslot[2 * l + 1];
     // L_ik = A_ik * Uinv_k
     block_mm<T>(b, M + sik * bb, M + dk * bb, M + sik * bb, 0);
-    __syncthreads();
+    sync_global();
     for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
       const int skj = upd[2 * u], sij = upd[2 * u + 1];
       block_mm<T>(b, M + sik * bb, M + skj * bb, M + sij * bb, 1);
     }
-    __syncthreads();
+    sync_global();
   }
   // pivot block: invert in place
   T* D = M + diag_slot[i] * bb;

@@ -1,0 +1,102 @@
+"""Parity at the full 16x16x8, p=3 size in the launch configuration the
+benchmark times: sampled element outputs against the oracle computed one by
+one from host-generated inputs, and the uncondensed residual checked on
+sampled element rows and face rows on the host."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import element_inputs, trace_rhs
+from synth.matrices import workload
+
+from gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+api = pytest.importorskip("paper_1605_01020_amd.api")
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def full1():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import synth.device as sd
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    wl = workload(1)
+    mc = wl.meshes[0]
+    spec, hm = mc.spec, mc.mesh
+    ctx = api.Context()
+    mesh = api.Mesh(ctx, hm.elem_faces(), hm.n_face, spec.b)
+    _say(f"generate config 1 inputs E={hm.n_elem}")
+    d = sd.gen_blocks(spec, wl.seed, 0, hm.n_elem, which="ABCDF")
+    G = sd.gen_trace_rhs(spec, wl.seed, 0, hm.n_face)
+    solver = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
+    _say("config 1 fp64 solve")
+    z, u, info = solver.solve_fp64(d["A"], d["B"], d["C"], d["D"], d["F"], G, rtol=wl.rtol)
+    ctx.sync_status()
+    yield wl, spec, hm, ctx, mesh, d, G, solver, z, u, info
+    del d
+    torch.cuda.empty_cache()
+
+
+SAMPLE = [0, 777, 2047]
+
+
+def test_fullsize_condense_sampled(full1):
+    wl, spec, hm, ctx, mesh, d, G, solver, z, u, info = full1
+    for e in SAMPLE:
+        blk = element_inputs(spec, wl.seed, 0, e)
+        Ke, re, _ = oracle.condense_element(blk["A"], blk["B"], blk["C"], blk["D"], blk["F"])
+        assert rel(solver.fac["Ke"][e].cpu().numpy(), Ke) <= 1e-12
+        assert rel(solver.fac["r"][e].cpu().numpy(), re) <= 1e-12
+
+
+def test_fullsize_fp64_residual_sampled(full1):
+    wl, spec, hm, ctx, mesh, d, G, solver, z, u, info = full1
+    assert info["converged"] and info["rel_resid"] <= wl.rtol
+    _, _, sums = api.residual_full(ctx, mesh, d["A"], d["B"], d["C"], d["D"], d["F"], G, z, u)
+    s = sums.cpu().numpy()
+    scale = np.sqrt(s[2] + s[3])
+    assert np.sqrt(s[0] + s[1]) / scale <= wl.rtol
+    ef = hm.elem_faces()
+    b = spec.b
+    uh = u.cpu().numpy()
+    Gh = G.cpu().numpy()
+    # element rows: F_e - A_e z_e - B_e u_e, on the host from host-generated blocks
+    for e in SAMPLE:
+        blk = element_inputs(spec, wl.seed, 0, e)
+        ue = (ef[e][:, None] * b + np.arange(b)[None, :]).ravel()
+        r = blk["F"] - blk["A"] @ z[e].cpu().numpy() - blk["B"] @ uh[ue]
+        assert np.linalg.norm(r) <= wl.rtol * scale
+    # a face row: G_f - sum over its elements of (C_e z_e + D_e u_e) on that face
+    f = int(ef[777][1])
+    owners = [(e, a) for e in range(hm.n_elem) for a in range(6) if ef[e][a] == f]
+    assert len(owners) == 2
+    rg = Gh[f * b:(f + 1) * b].copy()
+    np.testing.assert_allclose(rg, trace_rhs(spec, wl.seed, 0, hm.n_face, first=f * b, count=b), rtol=2e-14)
+    for e, a in owners:
+        blk = element_inputs(spec, wl.seed, 0, e, which="CD")
+        ue = (ef[e][:, None] * b + np.arange(b)[None, :]).ravel()
+        rg -= (blk["C"] @ z[e].cpu().numpy() + blk["D"] @ uh[ue])[a * b:(a + 1) * b]
+    assert np.linalg.norm(rg) <= wl.rtol * scale
+
+
+def test_fullsize_mixed_refinement(full1):
+    from paper_1605_01020_amd import F32
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    wl, spec, hm, ctx, mesh, d, G, solver, z, u, info = full1
+    s2 = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
+    _say("config 1 mixed fp32 solve")
+    z2, u2, info2 = s2.solve_mixed(d["A"], d["B"], d["C"], d["D"], d["F"], G, tol=1e-8, prec=F32)
+    ctx.sync_status()
+    assert info2["converged_full"], info2["rho_hist"]
+    eu = rel(u2.cpu().numpy(), u.cpu().numpy())
+    ez = rel(z2.cpu().numpy(), z.cpu().numpy())
+    _say(f"mixed vs fp64: uhat {eu:.2e} z {ez:.2e} rho {info2['rho_hist']} iters {info2['iters']}")
+    assert eu <= 1e-7 and ez <= 1e-7

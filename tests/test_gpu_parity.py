@@ -36,6 +36,14 @@ def ctx():
     torch.cuda.synchronize()
 
 
+@pytest.fixture(autouse=True)
+def _clean_status(request):
+    # a failed test must not leave a latched device error for the next one
+    if "ctx" in request.fixturenames:
+        request.getfixturevalue("ctx").clear_status()
+    yield
+
+
 def _mesh(ctx, m, spec, ordering="colour"):
     return api.Mesh(ctx, m.elem_faces(), m.n_face, spec.b, ordering=ordering)
 
@@ -80,16 +88,17 @@ def test_condense_parity(ctx, dims, p):
         assert rel(fac["Ke"][e].cpu().numpy(), Ke) <= 1e-12
         assert rel(fac["r"][e].cpu().numpy(), re) <= 1e-12
         # factor properties that hold for any partial-pivoting sequence
-        LU = fac["LU"][e].cpu().numpy()
         perm = fac["perm"][e].cpu().numpy()
         assert sorted(perm.tolist()) == list(range(spec.n))
+        # row i of the factors of P A is stored in row perm[i]
+        LU = fac["LU"][e].cpu().numpy()[perm]
         L = np.tril(LU, -1) + np.eye(spec.n)
         U = np.triu(LU)
         PA = blk["A"][perm]
         assert rel(L @ U, PA) <= 1e-13
         assert np.abs(np.tril(LU, -1)).max() <= 1.0 + 1e-12  # partial pivoting bound
-        assert rel(L @ fac["U12"][e].cpu().numpy(), blk["B"][perm]) <= 1e-13
-        assert rel(L @ fac["w"][e].cpu().numpy(), blk["F"][perm]) <= 1e-13
+        assert rel(L @ fac["U12"][e].cpu().numpy()[perm], blk["B"][perm]) <= 1e-13
+        assert rel(L @ fac["w"][e].cpu().numpy()[perm], blk["F"][perm]) <= 1e-13
         assert rel(fac["L21"][e].cpu().numpy() @ U, blk["C"]) <= 1e-13
 
 
@@ -285,3 +294,20 @@ def test_gmres_failure_paths(ctx):
     assert ei.value.status == -4
     with pytest.raises(api.IedgError):
         api.gmres_solve(ctx, mesh, K, M, R, restart=0, rtol=1e-10)
+
+
+@pytest.mark.parametrize("dims,p", CASES)
+def test_condense_parity_fp32(ctx, dims, p):
+    from paper_1605_01020_amd import F32
+    m, spec, blocks, G = host_case(dims, p)
+    _say(f"condense fp32 {dims} p={p}")
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=F32)
+    ctx.sync_status()
+    for e, blk in enumerate(blocks):
+        Ke, re, _ = oracle.condense_element(blk["A"], blk["B"], blk["C"], blk["D"], blk["F"])
+        ke = fac["Ke"][e].double().cpu().numpy()
+        rr = fac["r"][e].cpu().numpy()
+        assert np.isfinite(ke).all() and np.isfinite(rr).all()
+        assert rel(ke, Ke) <= 2e-5, (e, rel(ke, Ke))
+        assert rel(rr, re) <= 2e-5, (e, rel(rr, re))

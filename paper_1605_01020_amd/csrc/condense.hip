@@ -15,7 +15,7 @@
 //   for each panel [c0, c1):
 //     1. panel column (Crout order): M[c0:, c0:c1] = in - L[c0:, :c0] U[:c0, c0:c1]
 //        -- MFMA tiles of 256 x 64 fed from double-buffered LDS k-slabs
-//     2. panel factorisation in leaves of 8 columns held in registers:
+//     2. panel factorisation in leaves of 4 columns held in registers:
 //        each leaf first takes the updates of the panel's earlier leaves
 //        (left-looking, fused into its load), then partial pivoting with a
 //        workgroup argmax per column; the panel's L^{-1} is grown in LDS
@@ -32,7 +32,7 @@ namespace iedg {
 constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
 constexpr int NW = NT / 64;   // waves
-constexpr int LWT = 8;        // leaf width
+constexpr int LWT = 4;        // leaf width
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
 constexpr int LIS = CT + 1;   // LDS stride of L^{-1}
 
@@ -123,51 +123,47 @@ struct Tile {
   static_assert(AL >= 1 && BL >= 1 && RB * CB == 8, "tile shape");
 };
 
+// Per-thread global-load descriptors of one k-slab (compile-time counts).
 template <typename T, int TM, int TN>
-__device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
-                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+struct SlabLoader {
   typedef Tile<T, TM, TN> TL;
-  typedef Mfma<T> MF;
   typedef typename Pair<T>::v P2;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
-#pragma unroll
-  for (int rb = 0; rb < TL::RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::zero();
-  if (K <= 0) return;
-  const int nch = (K + KC - 1) / KC;
-  // per-thread load slots
   const T* aptr[TL::AL];
   int ak[TL::AL], arow[TL::AL];
-#pragma unroll
-  for (int q = 0; q < TL::AL; ++q) {
-    const int idx = tid + q * NT;
-    arow[q] = idx / (KC / 2);
-    ak[q] = 2 * (idx % (KC / 2));
-    const int row = r0 + arow[q];
-    aptr[q] = row < rlim ? el.lrow(row) : nullptr;
-  }
   const T* bbase[TL::BL];
   const double* bw[TL::BL];
   int bstride[TL::BL], bk[TL::BL], bcol[TL::BL], bn[TL::BL];
+  const int* sperm;
+  int K;
+
+  __device__ inline void init(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K_) {
+    const int tid = threadIdx.x;
+    sperm = el.sperm;
+    K = K_;
 #pragma unroll
-  for (int q = 0; q < TL::BL; ++q) {
-    const int idx = tid + q * NT;
-    bk[q] = idx / (TN / 2);
-    bcol[q] = 2 * (idx % (TN / 2));
-    const int col = c0 + bcol[q];
-    bn[q] = col >= clim ? 0 : (col + 1 >= clim ? 1 : 2);
-    bw[q] = nullptr;
-    bbase[q] = el.LU;
-    bstride[q] = 0;
-    if (col < el.n) { bbase[q] = el.LU + col; bstride[q] = el.n; }
-    else if (col < el.N) { bbase[q] = el.U12 + (col - el.n); bstride[q] = el.t; }
-    else { bw[q] = el.w; }
+    for (int q = 0; q < TL::AL; ++q) {
+      const int idx = tid + q * NT;
+      arow[q] = idx / (KC / 2);
+      ak[q] = 2 * (idx % (KC / 2));
+      const int row = r0 + arow[q];
+      aptr[q] = row < rlim ? el.lrow(row) : nullptr;
+    }
+#pragma unroll
+    for (int q = 0; q < TL::BL; ++q) {
+      const int idx = tid + q * NT;
+      bk[q] = idx / (TN / 2);
+      bcol[q] = 2 * (idx % (TN / 2));
+      const int col = c0 + bcol[q];
+      bn[q] = col >= clim ? 0 : (col + 1 >= clim ? 1 : 2);
+      bw[q] = nullptr;
+      bbase[q] = el.LU;
+      bstride[q] = 0;
+      if (col < el.n) { bbase[q] = el.LU + col; bstride[q] = el.n; }
+      else if (col < el.N) { bbase[q] = el.U12 + (col - el.n); bstride[q] = el.t; }
+      else { bw[q] = el.w; }
+    }
   }
-  P2 ra[2][TL::AL], rbv[2][TL::BL];
-  auto gload = [&](int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) {
+  __device__ inline void load(int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) const {
     const int k0 = ch * KC;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
@@ -183,21 +179,17 @@ __device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, in
       P2 v;
       v.x = T(0); v.y = T(0);
       if (k < K && bn[q]) {
-        const size_t pr = (size_t)el.sperm[k];
-        if (bw[q]) {
-          v.x = (T)bw[q][pr];
-        } else if (bn[q] == 2) {
-          v = *reinterpret_cast<const P2*>(bbase[q] + pr * bstride[q]);
-        } else {
-          v.x = bbase[q][pr * bstride[q]];
-        }
+        const size_t pr = (size_t)sperm[k];
+        if (bw[q]) v.x = (T)bw[q][pr];
+        else if (bn[q] == 2) v = *reinterpret_cast<const P2*>(bbase[q] + pr * bstride[q]);
+        else v.x = bbase[q][pr * bstride[q]];
       }
       vb[q] = v;
     }
-  };
-  auto sstore = [&](int stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) {
-    T* As = smem + stage * TL::STAGE;
-    T* Bs = As + KC * TL::SA;
+  }
+  __device__ inline void store(T* stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) const {
+    T* As = stage;
+    T* Bs = stage + KC * TL::SA;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
       As[ak[q] * TL::SA + arow[q]] = va[q].x;
@@ -205,35 +197,77 @@ __device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, in
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) *reinterpret_cast<P2*>(Bs + bk[q] * TL::SB + bcol[q]) = vb[q];
-  };
-  gload(0, ra[0], rbv[0]);
-  if (nch > 1) gload(1, ra[1], rbv[1]);
-  sstore(0, ra[0], rbv[0]);
-  if (nch > 2) gload(2, ra[0], rbv[0]);
+  }
+};
+
+template <typename T, int TM, int TN>
+__device__ inline void slab_mma(const T* stage, int wr0, int wc0,
+                                typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+  typedef Tile<T, TM, TN> TL;
+  typedef Mfma<T> MF;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const T* As = stage + wr0 + li + lg * TL::SA;
+  const T* Bs = stage + KC * TL::SA + wc0 + li + lg * TL::SB;
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    T av[TL::RB], bv[TL::CB];
+#pragma unroll
+    for (int rb = 0; rb < TL::RB; ++rb) av[rb] = As[4 * ks * TL::SA + 16 * rb];
+#pragma unroll
+    for (int cb = 0; cb < TL::CB; ++cb) bv[cb] = Bs[4 * ks * TL::SB + 16 * cb];
+#pragma unroll
+    for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
+  }
+}
+
+// acc = L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN tile;
+// rows >= rlim, cols >= clim and k >= K read as zero.  Waves are stacked
+// along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
+// wave 64 x 32).  k-slabs of KC go through two LDS stages; each thread keeps
+// the global loads of the next two slabs in flight in two register buffers.
+// The slab loop is unrolled by two so that stage and buffer indices are
+// compile-time constants.
+template <typename T, int TM, int TN>
+__device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
+                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+  typedef Tile<T, TM, TN> TL;
+  typedef Mfma<T> MF;
+  typedef typename Pair<T>::v P2;
+  const int wv = threadIdx.x >> 6;
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
+#pragma unroll
+  for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::zero();
+  if (K <= 0) return;
+  const int nch = (K + KC - 1) / KC;
+  SlabLoader<T, TM, TN> ld;
+  ld.init(el, r0, rlim, c0, clim, K);
+  T* S0 = smem;
+  T* S1 = smem + TL::STAGE;
+  P2 a0[TL::AL], b0[TL::BL], a1[TL::AL], b1[TL::BL];
+  ld.load(0, a0, b0);
+  if (nch > 1) ld.load(1, a1, b1);
+  ld.store(S0, a0, b0);
+  if (nch > 2) ld.load(2, a0, b0);
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int nxt = ch + 1;
-    if (nxt < nch) {
-      if (nxt & 1) sstore(1, ra[1], rbv[1]); else sstore(0, ra[0], rbv[0]);
-      if (nxt + 2 < nch) {
-        if (nxt & 1) gload(nxt + 2, ra[1], rbv[1]); else gload(nxt + 2, ra[0], rbv[0]);
-      }
+  for (int ch = 0; ch < nch; ch += 2) {
+    if (ch + 1 < nch) {
+      ld.store(S1, a1, b1);
+      if (ch + 3 < nch) ld.load(ch + 3, a1, b1);
     }
-    const T* As = smem + (ch & 1) * TL::STAGE;
-    const T* Bs = As + KC * TL::SA;
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      T av[TL::RB], bv[TL::CB];
-#pragma unroll
-      for (int rb = 0; rb < TL::RB; ++rb) av[rb] = As[(4 * ks + lg) * TL::SA + wr0 + 16 * rb + li];
-#pragma unroll
-      for (int cb = 0; cb < TL::CB; ++cb) bv[cb] = Bs[(4 * ks + lg) * TL::SB + wc0 + 16 * cb + li];
-#pragma unroll
-      for (int rb = 0; rb < TL::RB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
-    }
+    slab_mma<T, TM, TN>(S0, wr0, wc0, acc);
     __syncthreads();
+    if (ch + 1 < nch) {
+      if (ch + 2 < nch) {
+        ld.store(S0, a0, b0);
+        if (ch + 4 < nch) ld.load(ch + 4, a0, b0);
+      }
+      slab_mma<T, TM, TN>(S1, wr0, wc0, acc);
+      __syncthreads();
+    }
   }
 }
 
@@ -271,9 +305,8 @@ __device__ inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Ti
 
 // ---- panel factorisation -------------------------------------------------
 struct PanelSmem {
-  double red_v[NW];
-  int red_i[NW];
-  int piv;
+  double red_v[2][NW];   // double-buffered by column parity
+  int red_i[2][NW];
 };
 
 template <typename T>
@@ -281,9 +314,8 @@ struct PanelBufs {
   T* Linv;   // CT x LIS: L_pp^{-1} of the panel's factored columns so far
   T* Xu;     // CT x LWT: rows [c0, cs) of the leaf columns (input / U)
   T* Lb;     // LWT x CT: L(cs:ce, c0:ce) rows of the leaf
-  T* prow;   // LWT: pivot row of the current column
-  T* krow;   // LWT
-  T* ul;     // LWT x LWT: U of the leaf's diagonal block
+  T* prow;   // 2 x LWT: pivot row of the current column (by column parity)
+  T* krow;   // 2 x LWT: displaced row
   PanelSmem* ps;
 };
 
@@ -318,47 +350,69 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, cons
       sync_global();
     }
     // (b) load the leaf rows with the panel's earlier updates applied
+    // rows of A (positions cs + tid + NT q) and of C (n + tid + NT q); the L
+    // values of a row in columns [c0, cs) are contiguous: read them 8 at a
+    // time for all owned rows together so the loads overlap
     T x[QA][LWT];
+    T xc[QC][LWT];
+    const T* lra[QA];
+    const T* lrc[QC];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       const int row = cs + tid + NT * q;
+      lra[q] = row < n ? el.lrow(row) + c0 : nullptr;
 #pragma unroll
-      for (int j = 0; j < LWT; ++j) x[q][j] = T(0);
-      if (row < n) {
-#pragma unroll
-        for (int j = 0; j < LWT; ++j)
-          if (j < lw) x[q][j] = el.ld(row, cs + j);
-        const T* lr = el.lrow(row) + c0;
-        for (int k = 0; k < kp; ++k) {
-          const T l = lr[k];
-#pragma unroll
-          for (int j = 0; j < LWT; ++j) x[q][j] -= l * pb.Xu[k * LWT + j];
-        }
-      }
+      for (int j = 0; j < LWT; ++j) x[q][j] = (row < n && j < lw) ? el.ld(row, cs + j) : T(0);
     }
-    T xc[QC][LWT];
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
       const int row = n + tid + NT * q;
+      lrc[q] = row < N ? el.lrow(row) + c0 : nullptr;
 #pragma unroll
-      for (int j = 0; j < LWT; ++j) xc[q][j] = T(0);
-      if (row < N) {
+      for (int j = 0; j < LWT; ++j) xc[q][j] = (row < N && j < lw) ? el.ld(row, cs + j) : T(0);
+    }
+    // KB columns of L per round trip (kp is a multiple of LWT; the tail of
+    // the last group reads zeros)
+    constexpr int KB = QA <= 3 ? 16 : 4;
+    for (int k0 = 0; k0 < kp; k0 += KB) {
+      T la[QA][KB], lc[QC][KB];
 #pragma unroll
-        for (int j = 0; j < LWT; ++j)
-          if (j < lw) xc[q][j] = el.ld(row, cs + j);
-        const T* lr = el.lrow(row) + c0;
-        for (int k = 0; k < kp; ++k) {
-          const T l = lr[k];
+      for (int q = 0; q < QA; ++q)
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) xc[q][j] -= l * pb.Xu[k * LWT + j];
+        for (int kk = 0; kk < KB; ++kk) la[q][kk] = (lra[q] && k0 + kk < kp) ? lra[q][k0 + kk] : T(0);
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) lc[q][kk] = (lrc[q] && k0 + kk < kp) ? lrc[q][k0 + kk] : T(0);
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        if (k0 + kk < kp) {
+          T u[LWT];
+#pragma unroll
+          for (int j = 0; j < LWT; ++j) u[j] = pb.Xu[(k0 + kk) * LWT + j];
+#pragma unroll
+          for (int q = 0; q < QA; ++q)
+#pragma unroll
+            for (int j = 0; j < LWT; ++j) x[q][j] -= la[q][kk] * u[j];
+#pragma unroll
+          for (int q = 0; q < QC; ++q)
+#pragma unroll
+            for (int j = 0; j < LWT; ++j) xc[q][j] -= lc[q][kk] * u[j];
         }
       }
     }
-    // (c) partial pivoting over positions [k, n), one column at a time
+    // (c) partial pivoting over positions [k, n), one column at a time.  The
+    // LDS scratch alternates by column parity, so two barriers per column
+    // suffice: a wave can only overwrite a buffer after every wave has
+    // passed the first barrier of the next column, i.e. finished reading it.
 #pragma unroll
     for (int kk = 0; kk < LWT; ++kk) {
       if (kk < lw) {
-        const int k = cs + kk;
+        const int k = cs + kk, par = kk & 1;
+        double* rv = pb.ps->red_v[par];
+        int* ri = pb.ps->red_i[par];
+        T* prow = pb.prow + par * LWT;
+        T* krow = pb.krow + par * LWT;
         double best = -1.0;
         int bidx = INT_MAX;
 #pragma unroll
@@ -373,14 +427,14 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, cons
           const int oi = __shfl_xor(bidx, off, kWave);
           if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
-        if (lane == 0) { pb.ps->red_v[wv] = best; pb.ps->red_i[wv] = bidx; }
+        if (lane == 0) { rv[wv] = best; ri[wv] = bidx; }
         __syncthreads();
-        best = pb.ps->red_v[0];
-        bidx = pb.ps->red_i[0];
+        best = rv[0];
+        bidx = ri[0];
 #pragma unroll
         for (int i = 1; i < NW; ++i) {
-          const double ov = pb.ps->red_v[i];
-          const int oi = pb.ps->red_i[i];
+          const double ov = rv[i];
+          const int oi = ri[i];
           if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
         int piv = bidx;
@@ -394,11 +448,11 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, cons
           for (int q = 0; q < QA; ++q)
             if (q == po / NT)
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) pb.prow[j] = x[q][j];
+              for (int j = 0; j < LWT; ++j) prow[j] = x[q][j];
         }
         if (tid == kk) {
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) pb.krow[j] = x[0][j];
+          for (int j = 0; j < LWT; ++j) krow[j] = x[0][j];
         }
         __syncthreads();
         if (piv != k && tid == po % NT) {
@@ -406,21 +460,20 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, cons
           for (int q = 0; q < QA; ++q)
             if (q == po / NT)
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) x[q][j] = pb.krow[j];
+              for (int j = 0; j < LWT; ++j) x[q][j] = krow[j];
         }
         if (tid == kk) {
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) x[0][j] = pb.prow[j];
+          for (int j = 0; j < LWT; ++j) x[0][j] = prow[j];
         }
         if (tid == 0) {
           const int tmp = sperm[k];
           sperm[k] = sperm[piv];
           sperm[piv] = tmp;
         }
-        if (tid < LWT) pb.ul[kk * LWT + tid] = pb.prow[tid];
         T u[LWT];
 #pragma unroll
-        for (int j = 0; j < LWT; ++j) u[j] = pb.prow[j];
+        for (int j = 0; j < LWT; ++j) u[j] = prow[j];
         const T ukk = u[kk];
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -441,7 +494,6 @@ __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, cons
             for (int j = kk + 1; j < LWT; ++j) xc[q][j] -= l * u[j];
           }
         }
-        __syncthreads();
       }
     }
     // (d) write the leaf back (positions now final for rows [cs, ce))
@@ -514,7 +566,7 @@ template <typename T>
 struct CondenseSmem {
   static constexpr int GEMM = 2 * (KC * (256 + 1 + 64 + 2));   // elements, both tile shapes
   static size_t bytes(int n) {
-    return sizeof(T) * (GEMM + CT * LIS + CT * LWT + LWT * CT + 2 * LWT + LWT * LWT) + sizeof(PanelSmem) + 16 +
+    return sizeof(T) * (GEMM + CT * LIS + CT * LWT + LWT * CT + 4 * LWT + LWT * LWT) + sizeof(PanelSmem) + 16 +
            sizeof(int) * n;
   }
 };
@@ -532,9 +584,8 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   pb.Xu = pb.Linv + CT * LIS;
   pb.Lb = pb.Xu + CT * LWT;
   pb.prow = pb.Lb + LWT * CT;
-  pb.krow = pb.prow + LWT;
-  pb.ul = pb.krow + LWT;
-  pb.ps = reinterpret_cast<PanelSmem*>(pb.ul + LWT * LWT);
+  pb.krow = pb.prow + 2 * LWT;
+  pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * LWT + LWT * LWT);
   int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
 
   Elem<T> el;

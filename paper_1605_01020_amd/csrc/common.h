@@ -73,6 +73,28 @@ __device__ inline void sync_global() {
   asm volatile("buffer_inv sc0" ::: "memory");
 }
 
+// Dot product of a contiguous row (len values) with an LDS vector by one
+// wave; each lane keeps 8 loads in flight per round trip.
+template <typename T>
+__device__ inline double wave_dot(const T* row, const double* vec, int len) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int k0 = lane; k0 < len; k0 += 64 * 8) {
+    T v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + 64 * j;
+      v[j] = k < len ? row[k] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + 64 * j;
+      if (k < len) s += (double)v[j] * vec[k];
+    }
+  }
+  return wave_sum(s);
+}
+
 // Device status word: first failing index (element or block row) + code.
 struct DeviceStatus {
   int32_t code;   // 0 = ok, otherwise an iedg_status value

@@ -718,10 +718,7 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int i1 = min(i0 + 64, n), bw = i1 - i0;
     for (int i = i0 + wv; i < i1; i += RTHR / 64) {
-      double s = 0.0;
-      const T* row = L + (size_t)sp[i] * n;
-      for (int k = lane; k < i0; k += 64) s += (double)row[k] * y[k];
-      s = wave_sum(s);
+      const double s = wave_dot<T>(L + (size_t)sp[i] * n, y, i0);
       if (lane == 0) y[i] -= s;
     }
     for (int q = tid; q < 64 * 64; q += RTHR) {
@@ -742,10 +739,7 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   for (int i = tid; i < n; i += RTHR) w[(size_t)e * n + sp[i]] = y[i];
   const T* L2 = L21 + (size_t)e * t * n;
   for (int i = wv; i < t; i += RTHR / 64) {
-    double s = 0.0;
-    const T* row = L2 + (size_t)i * n;
-    for (int k = lane; k < n; k += 64) s += (double)row[k] * y[k];
-    s = wave_sum(s);
+    const double s = wave_dot<T>(L2 + (size_t)i * n, y, n);
     if (lane == 0) r[(size_t)e * t + i] = -s;
   }
 }

@@ -28,10 +28,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
   __syncthreads();
   const T* U12e = U12 + (size_t)e * n * t;
   for (int i = wv; i < n; i += LWAVES) {
-    const T* row = U12e + (size_t)sp[i] * t;
-    double s = 0.0;
-    for (int k = lane; k < t; k += 64) s += (double)row[k] * ue[k];
-    s = wave_sum(s);
+    const double s = wave_dot<T>(U12e + (size_t)sp[i] * t, ue, t);
     if (lane == 0) y[i] = w[(size_t)e * n + sp[i]] - s;
   }
   __syncthreads();
@@ -41,10 +38,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
     const int i0 = bi * 64, i1 = min(i0 + 64, n), bw = i1 - i0;
     // y[i0:i1] -= U[i0:i1, i1:n] z[i1:n]   (z stored in y beyond i1)
     for (int i = i0 + wv; i < i1; i += LWAVES) {
-      const T* row = U + (size_t)sp[i] * n;
-      double s = 0.0;
-      for (int k = i1 + lane; k < n; k += 64) s += (double)row[k] * y[k];
-      s = wave_sum(s);
+      const double s = wave_dot<T>(U + (size_t)sp[i] * n + i1, y + i1, n - i1);
       if (lane == 0) y[i] -= s;
     }
     for (int q = tid; q < 64 * 64; q += LTHR) {
@@ -89,12 +83,7 @@ __global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b
   const double *Ae = A + e * nn, *Be = B + e * nt, *Ce = C + e * nt, *De = D + e * tt;
   double srf = 0.0, sf = 0.0;  // per-wave partials (lane 0)
   for (int i = wv; i < n; i += LWAVES) {
-    const double* ra = Ae + (size_t)i * n;
-    const double* rb = Be + (size_t)i * t;
-    double s = 0.0;
-    for (int k = lane; k < n; k += 64) s += ra[k] * ze[k];
-    for (int k = lane; k < t; k += 64) s += rb[k] * ue[k];
-    s = wave_sum(s);
+    const double s = wave_dot<double>(Ae + (size_t)i * n, ze, n) + wave_dot<double>(Be + (size_t)i * t, ue, t);
     if (lane == 0) {
       const double f = F[(size_t)e * n + i];
       const double v = f - s;
@@ -104,12 +93,7 @@ __global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b
     }
   }
   for (int i = wv; i < t; i += LWAVES) {
-    const double* rc = Ce + (size_t)i * n;
-    const double* rd = De + (size_t)i * t;
-    double s = 0.0;
-    for (int k = lane; k < n; k += 64) s += rc[k] * ze[k];
-    for (int k = lane; k < t; k += 64) s += rd[k] * ue[k];
-    s = wave_sum(s);
+    const double s = wave_dot<double>(Ce + (size_t)i * n, ze, n) + wave_dot<double>(De + (size_t)i * t, ue, t);
     if (lane == 0) q[(size_t)e * t + i] = s;
   }
   if (lane == 0) { acc[2 * wv] = srf; acc[2 * wv + 1] = sf; }

@@ -25,11 +25,20 @@ __global__ __launch_bounds__(STHR) void assemble_k_kernel(int b, int t, const in
   const T* p0 = Ke + (size_t)(src0 / 36) * tt + (size_t)((src0 % 36) / 6) * b * t + (size_t)(src0 % 6) * b;
   const T* p1 = src1 >= 0 ? Ke + (size_t)(src1 / 36) * tt + (size_t)((src1 % 36) / 6) * b * t + (size_t)(src1 % 6) * b
                           : nullptr;
-  for (int i = threadIdx.x; i < bb; i += STHR) {
-    const int rr = i / b, cc = i % b;
-    T v = p0[(size_t)rr * t + cc];
-    if (p1) v += p1[(size_t)rr * t + cc];
-    tile[rr * (b + 1) + cc] = v;
+  for (int i0 = threadIdx.x; i0 < bb; i0 += STHR * 8) {
+    T v0[8], v1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + STHR * j;
+      const int rr = i / b, cc = i % b;
+      v0[j] = i < bb ? p0[(size_t)rr * t + cc] : T(0);
+      v1[j] = (p1 && i < bb) ? p1[(size_t)rr * t + cc] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = i0 + STHR * j;
+      if (i < bb) tile[(i / b) * (b + 1) + i % b] = p1 ? v0[j] + v1[j] : v0[j];
+    }
   }
   __syncthreads();
   T* out = Kbsr + (size_t)s * bb;
@@ -289,6 +298,140 @@ __global__ __launch_bounds__(STHR) void ilu0_level_kernel(int b, const int32_t* 
   }
 }
 
+// One level of BILU(0) with both operands of every block product staged in
+// LDS (b x b blocks, column-major, stride b + 1): sX holds A_ik and then
+// L_ik = A_ik U_kk^{-1}; sB holds the right operand (U_kk^{-1}, then each
+// U_kj).  Products run on MFMA with 16 x 16 tiles dealt round-robin to the
+// four waves; A_ij -= L_ik U_kj is applied tile by tile to global memory.
+// Copy up to two b x b blocks from global to LDS (stride b + 1), 8 loads in
+// flight per thread per block.
+template <typename T>
+__device__ inline void lds_block_load2(const T* g0, T* s0, const T* g1, T* s1, int b) {
+  const int ls = b + 1, bb = b * b;
+  for (int q0 = threadIdx.x; q0 < bb; q0 += STHR * 8) {
+    T v0[8], v1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = q0 + STHR * j;
+      v0[j] = q < bb ? g0[q] : T(0);
+      v1[j] = (g1 && q < bb) ? g1[q] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int q = q0 + STHR * j;
+      if (q < bb) {
+        const int c = q / b, r = q % b;
+        s0[c * ls + r] = v0[j];
+        if (g1) s1[c * ls + r] = v1[j];
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void lds_block_mm(int b, const T* sA, const T* sB, typename Mfma<T>::acc_t (&acc)[16]) {
+  typedef Mfma<T> MF;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int nt = (b + 15) / 16, ntiles = nt * nt, ls = b + 1;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    acc[q] = MF::zero();
+    const int tI = wv + 4 * q;
+    if (tI < ntiles) {
+      const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+      const int ia = i0 + li, jb = j0 + li;
+      for (int k0 = 0; k0 < b; k0 += 4) {
+        const int k = k0 + lg;
+        const T av = (ia < b && k < b) ? sA[k * ls + ia] : T(0);
+        const T bv = (jb < b && k < b) ? sB[jb * ls + k] : T(0);
+        acc[q] = MF::mac(av, bv, acc[q]);
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32_t* rows, const int32_t* diag_slot,
+                                                              const int32_t* lptr, const int32_t* lslot,
+                                                              const int32_t* uptr, const int32_t* upd, T* M,
+                                                              DeviceStatus* status) {
+  typedef Mfma<T> MF;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ls = b + 1;
+  T* sX = reinterpret_cast<T*>(smem_raw);   // b x ls: A_ik, then L_ik
+  T* sB = sX + (size_t)b * ls;              // b x ls: right operand
+  T* sC = sB + (size_t)b * ls;              // b x ls: block being updated
+  int* piv = reinterpret_cast<int*>(sC + (size_t)b * ls);
+  double* rv = reinterpret_cast<double*>(piv + 128);
+  int* ri = reinterpret_cast<int*>(rv + 1);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15;
+  const int nt = (b + 15) / 16, ntiles = nt * nt;
+  const int i = rows[blockIdx.x];
+  const size_t bb = (size_t)b * b;
+  typename MF::acc_t acc[16];
+  for (int l = lptr[i]; l < lptr[i + 1]; ++l) {
+    const int sik = lslot[2 * l], dk = lslot[2 * l + 1];
+    lds_block_load2<T>(M + sik * bb, sX, M + dk * bb, sB, b);
+    __syncthreads();
+    lds_block_mm<T>(b, sX, sB, acc);
+    __syncthreads();
+    // L_ik into sX (LDS), then to M[sik] from LDS (coalesced)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int tI = wv + 4 * q;
+      if (tI < ntiles) {
+        const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = i0 + MF::row(lane, v), c = j0 + li;
+          if (r < b && c < b) sX[c * ls + r] = acc[q][v];
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < (int)bb; q += STHR) M[sik * bb + q] = sX[(q / b) * ls + q % b];
+    for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
+      const int skj = upd[2 * u], sij = upd[2 * u + 1];
+      lds_block_load2<T>(M + skj * bb, sB, M + sij * bb, sC, b);
+      __syncthreads();
+      lds_block_mm<T>(b, sX, sB, acc);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int tI = wv + 4 * q;
+        if (tI < ntiles) {
+          const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = i0 + MF::row(lane, v), c = j0 + li;
+            if (r < b && c < b) sC[c * ls + r] -= acc[q][v];
+          }
+        }
+      }
+      __syncthreads();
+      T* C = M + sij * bb;
+      for (int q = threadIdx.x; q < (int)bb; q += STHR) C[q] = sC[(q / b) * ls + q % b];
+      __syncthreads();
+    }
+    sync_global();
+  }
+  // pivot block: invert in place (row-major staging in sX)
+  T* Dg = M + diag_slot[i] * bb;
+  lds_block_load2<T>(Dg, sC, nullptr, nullptr, b);
+  __syncthreads();
+  for (int q = threadIdx.x; q < (int)bb; q += STHR) {
+    const int c = q / b, r = q % b;
+    sX[r * ls + c] = sC[c * ls + r];
+  }
+  __syncthreads();
+  const bool ok = gj_invert<T>(sX, b, piv, rv, ri);
+  if (!ok && threadIdx.x == 0) latch_status(status, IEDG_ERR_SINGULAR, i);
+  for (int q = threadIdx.x; q < (int)bb; q += STHR) {
+    const int c = q / b, r = q % b;
+    Dg[q] = sX[r * ls + c];
+  }
+}
+
 template <typename T>
 static size_t elem_size() { return sizeof(T); }
 
@@ -376,8 +519,25 @@ iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh m, iedg_prec prec, cons
   if (Kbsr != Mbsr)
     IEDG_HIP(ctx, hipMemcpyAsync(Mbsr, Kbsr, es * m->nnzb * m->b * m->b, hipMemcpyDeviceToDevice, stream));
   const size_t smem = es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
+  const size_t smem2 = 3 * es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
+  const bool staged = smem2 <= 160 * 1024;
   for (int l = 0; l < m->n_levels; ++l) {
     const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
+    if (staged) {
+      if (prec == IEDG_F64) {
+        auto k = ilu0_level_lds_kernel<double>;
+        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem2));
+        hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem2, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (double*)Mbsr, ctx->d_status);
+      } else {
+        auto k = ilu0_level_lds_kernel<float>;
+        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem2));
+        hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem2, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (float*)Mbsr, ctx->d_status);
+      }
+      IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
+      continue;
+    }
     if (prec == IEDG_F64) {
       auto k = ilu0_level_kernel<double>;
       IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));

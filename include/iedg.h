@@ -139,6 +139,32 @@ iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32_t n_local,
                               const double* F, double* w, double* r,
                               hipStream_t stream);
 
+/* Batched condensation (section 2.2.1, eq. LS) of several meshes whose
+ * elements share (n, t): one persistent launch over a work list of
+ * (segment, element) items, each item exactly as iedg_condense.  The plan
+ * copies the segment table to the device once; iedg_condense_batched only
+ * launches (it can be captured in a HIP graph).  Segment pointers must stay
+ * valid for the plan's lifetime. */
+typedef struct {
+  int32_t n_elem;
+  const double *A, *B, *C, *D, *F;
+  void* LU;
+  int32_t* perm;
+  void *U12, *L21;
+  double* w;
+  void* Ke;
+  double* r;
+} iedg_condense_segment;
+typedef struct iedg_batch_s* iedg_batch;
+iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
+                              int32_t n_local, int32_t n_trace_elem, iedg_prec prec,
+                              iedg_batch* out);
+iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch batch, hipStream_t stream);
+void iedg_batch_destroy(iedg_batch batch);
+/* Tuning of the condensation kernel: panel leaf width (4 or 8 columns)
+ * used for elements with n local dofs (process-wide; default 4). */
+iedg_status iedg_set_leaf_width(iedg_context ctx, int32_t n_local, int32_t leaf_width);
+
 /* ---- a2: assembly of K and R (section 2.2.1, eq. LS) ------------------ */
 /* Kbsr = sum_e P_e^T Ke_e P_e in the BSR layout of `mesh` (storage in
  * `prec`, same element type as Ke), R = G + sum_e P_e^T r_e.  Sums over the
@@ -183,6 +209,26 @@ iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,
                              const void* Kbsr, iedg_prec mprec, const void* Mbsr,
                              const double* R, double* x, const iedg_gmres_opts* opts,
                              iedg_gmres_info* info, hipStream_t stream);
+
+/* Capturable GMRES: one cycle of at most `steps` Arnoldi steps from x0 = 0,
+ * enqueued with no host synchronisation (it can be captured in a HIP
+ * graph).  Every Arnoldi kernel reads a device flag and returns at once
+ * after the inner stopping rule has fired, so the cycle stops where
+ * iedg_gmres_solve's first cycle would (GMRES(steps) with the same rules).
+ * The state owns the Krylov basis and scalars of one mesh; after the stream
+ * completes, iedg_gmres_state_read returns iterations, the true relative
+ * residual and whether it met rtol (a cycle is not restarted on the
+ * device: the caller may fall back to iedg_gmres_solve). */
+typedef struct iedg_gmres_state_s* iedg_gmres_state;
+iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
+                                    iedg_gmres_state* out);
+iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st,
+                               iedg_prec kprec, const void* Kbsr, iedg_prec mprec,
+                               const void* Mbsr, const double* R, double* x, double rtol,
+                               double inner_factor, hipStream_t stream);
+/* Synchronous read of the state's results (host). */
+iedg_status iedg_gmres_state_read(iedg_context ctx, iedg_gmres_state st, iedg_gmres_info* info);
+void iedg_gmres_state_destroy(iedg_gmres_state st);
 
 /* y = K x (kprec blocks, FP64 vectors); exposed for testing and refinement. */
 iedg_status iedg_spmv(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,

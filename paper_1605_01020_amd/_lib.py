@@ -29,6 +29,11 @@ class GmresInfo(ctypes.Structure):
                 ("rel_resid", c_double)]
 
 
+class CondenseSegment(ctypes.Structure):
+    _fields_ = [("n_elem", c_int32), ("A", P), ("B", P), ("C", P), ("D", P), ("F", P),
+                ("LU", P), ("perm", P), ("U12", P), ("L21", P), ("w", P), ("Ke", P), ("r", P)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "iedg_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.c_int]),
@@ -41,11 +46,20 @@ SIGNATURES = {
     "iedg_mesh_query": (c_int32, [P, ctypes.POINTER(MeshInfo), P, P, P, P]),
     "iedg_condense": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P,
                                 P, P, P, P, P, P, P, P]),
+    "iedg_batch_create": (c_int32, [P, c_int32, ctypes.POINTER(CondenseSegment), c_int32, c_int32,
+                                    c_int32, ctypes.POINTER(c_void_p)]),
+    "iedg_condense_batched": (c_int32, [P, P, P]),
+    "iedg_batch_destroy": (None, [P]),
+    "iedg_set_leaf_width": (c_int32, [P, c_int32, c_int32]),
     "iedg_condense_rhs": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P, P, P]),
     "iedg_assemble": (c_int32, [P, P, c_int32, P, P, P, P, P, P]),
     "iedg_factor_ilu0": (c_int32, [P, P, c_int32, P, P, P]),
     "iedg_gmres_solve": (c_int32, [P, P, c_int32, P, c_int32, P, P, P, ctypes.POINTER(GmresOpts),
                                    ctypes.POINTER(GmresInfo), P]),
+    "iedg_gmres_state_create": (c_int32, [P, P, c_int32, ctypes.POINTER(c_void_p)]),
+    "iedg_gmres_enqueue": (c_int32, [P, P, P, c_int32, P, c_int32, P, P, P, c_double, c_double, P]),
+    "iedg_gmres_state_read": (c_int32, [P, P, ctypes.POINTER(GmresInfo)]),
+    "iedg_gmres_state_destroy": (None, [P]),
     "iedg_spmv": (c_int32, [P, P, c_int32, P, P, P, P]),
     "iedg_ilu0_apply": (c_int32, [P, P, c_int32, P, P, P, P]),
     "iedg_backsolve_local": (c_int32, [P, P, c_int32, c_int32, P, P, P, P, P, P, P]),

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import F64, F32, BF16, GmresOpts, GmresInfo, MeshInfo
+from ._lib import F64, F32, BF16, CondenseSegment, GmresOpts, GmresInfo, MeshInfo
 
 PREC_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
 
@@ -144,6 +144,103 @@ def condense(ctx, A, B, C, D, F=None, prec=F64, out=None):
     ctx.check(ctx.L.iedg_condense(ctx.h, E, n, t, prec, _p(A), _p(B), _p(C), _p(D), _p(F),
                                   _p(LU), _p(perm), _p(U12), _p(L21), _p(w), _p(Ke), _p(r), _stream()))
     return o
+
+
+def alloc_condense_out(E, n, t, prec, device, with_rhs=True):
+    """Output buffers of iedg_condense for E elements."""
+    dt = PREC_DTYPE[prec]
+    o = {"LU": torch.empty((E, n, n), dtype=dt, device=device),
+         "perm": torch.empty((E, n), dtype=torch.int32, device=device),
+         "U12": torch.empty((E, n, t), dtype=dt, device=device),
+         "L21": torch.empty((E, t, n), dtype=dt, device=device),
+         "Ke": torch.empty((E, t, t), dtype=dt, device=device)}
+    if with_rhs:
+        o["w"] = torch.empty((E, n), dtype=torch.float64, device=device)
+        o["r"] = torch.empty((E, t), dtype=torch.float64, device=device)
+    return o
+
+
+class CondenseBatch:
+    """Plan for one persistent condensation launch over several segments
+    (meshes) with the same element size (iedg_batch_*).  `segments` is a
+    list of (inputs, outputs) dicts: inputs A, B, C, D, F (F may be None),
+    outputs as from alloc_condense_out.  Tensors must outlive the plan."""
+
+    def __init__(self, ctx, segments, prec=F64):
+        self.ctx = ctx
+        self._keep = segments
+        arr = (CondenseSegment * len(segments))()
+        n = t = None
+        for i, (inp, out) in enumerate(segments):
+            _check_dev(inp["A"], inp["B"], inp["C"], inp["D"], inp.get("F"))
+            E, n_i, _ = inp["A"].shape
+            t_i = inp["B"].shape[2]
+            if n is None:
+                n, t = n_i, t_i
+            elif (n, t) != (n_i, t_i):
+                raise ValueError("all segments of a batch share (n, t)")
+            a = arr[i]
+            a.n_elem = E
+            a.A, a.B, a.C, a.D = (inp[k].data_ptr() for k in "ABCD")
+            a.F = inp["F"].data_ptr() if inp.get("F") is not None else None
+            a.LU, a.perm, a.U12, a.L21, a.Ke = (out[k].data_ptr() for k in ("LU", "perm", "U12", "L21", "Ke"))
+            a.w = out["w"].data_ptr() if "w" in out else None
+            a.r = out["r"].data_ptr() if "r" in out else None
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.iedg_batch_create(ctx.h, len(segments), arr, n, t, prec, ctypes.byref(h)))
+        self.h, self.n, self.t, self.prec = h, n, t, prec
+
+    def run(self):
+        self.ctx.check(self.ctx.L.iedg_condense_batched(self.ctx.h, self.h, _stream()))
+
+    def close(self):
+        if self.h:
+            self.ctx.L.iedg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_leaf_width(ctx, n_local, leaf_width):
+    ctx.check(ctx.L.iedg_set_leaf_width(ctx.h, int(n_local), int(leaf_width)))
+
+
+class GmresState:
+    """Device-resident GMRES cycle (iedg_gmres_state_*): enqueue() issues no
+    host synchronisation, so it can be captured in a graph; read() returns
+    the outcome after the stream has completed."""
+
+    def __init__(self, ctx, mesh, steps):
+        self.ctx, self.mesh = ctx, mesh
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.iedg_gmres_state_create(ctx.h, mesh.h, int(steps), ctypes.byref(h)))
+        self.h, self.steps = h, steps
+
+    def enqueue(self, Kbsr, Mbsr, R, x, rtol, inner_factor=0.1, kprec=F64, mprec=F64):
+        _check_dev(Kbsr, Mbsr, R, x)
+        self.ctx.check(self.ctx.L.iedg_gmres_enqueue(self.ctx.h, self.mesh.h, self.h, kprec, _p(Kbsr), mprec,
+                                                     _p(Mbsr), _p(R), _p(x), float(rtol), float(inner_factor),
+                                                     _stream()))
+
+    def read(self):
+        info = GmresInfo()
+        self.ctx.check(self.ctx.L.iedg_gmres_state_read(self.ctx.h, self.h, ctypes.byref(info)))
+        return {"iters": info.iters, "converged": bool(info.converged), "rel_resid": info.rel_resid}
+
+    def close(self):
+        if self.h:
+            self.ctx.L.iedg_gmres_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def condense_rhs(ctx, fac, F, prec=F64, w=None, r=None):

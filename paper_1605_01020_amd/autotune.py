@@ -1,0 +1,89 @@
+"""Measured choice of the condensation kernel's panel leaf width.
+
+The panel factorisation of the condensation kernel works on leaves of 4 or
+8 columns (8 is built for n <= 1536).  For each element size the tuner
+times both on a device-generated sample of elements and keeps the faster;
+the table is stored as tuning.json beside this file and applied with
+iedg_set_leaf_width.
+
+    python -m paper_1605_01020_amd.autotune          # measure and write
+"""
+import json
+import os
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+LEAF_CHOICES = {2: (4, 8), 3: (4, 8), 4: (4,)}
+
+
+def _time_condense(ctx, spec, d, prec, reps):
+    import torch
+    from . import api
+    out = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=prec)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=prec, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ctx.sync_status()
+    return min(ts)
+
+
+def tune(ctx, ps=(2, 3, 4), n_elem=512, reps=3, seed=1605010203, log=print):
+    import torch
+    from . import api
+    from ._lib import F32
+    from synth import ElementSpec
+    import synth.device as sd
+    table = {"prec": "f32", "n_elem": n_elem, "entries": []}
+    for p in ps:
+        spec = ElementSpec(p)
+        d = sd.gen_blocks(spec, seed, 0, n_elem, which="ABCDF")
+        best = None
+        times = {}
+        for lw in LEAF_CHOICES[p]:
+            api.set_leaf_width(ctx, spec.n, lw)
+            ms = _time_condense(ctx, spec, d, F32, reps)
+            times[lw] = ms
+            log(f"p={p} n={spec.n} leaf={lw}: {ms:.2f} ms for {n_elem} elements")
+            if best is None or ms < times[best]:
+                best = lw
+        api.set_leaf_width(ctx, spec.n, best)
+        table["entries"].append({"p": p, "n": spec.n, "leaf_width": best,
+                                 "ms": {str(k): v for k, v in times.items()}})
+        del d
+        torch.cuda.empty_cache()
+    return table
+
+
+def apply_tuning(ctx, path=TUNING_PATH):
+    """Apply a stored table (no-op when none has been measured)."""
+    from . import api
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    for e in table.get("entries", []):
+        api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]))
+    return table
+
+
+def main():
+    import torch
+    from . import api
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    table = tune(ctx, log=lambda m: print(f"[autotune] {m}", flush=True))
+    out = sys.argv[1] if len(sys.argv) > 1 else TUNING_PATH
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(f"[autotune] wrote {out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,7 +32,7 @@ namespace iedg {
 constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
 constexpr int NW = NT / 64;   // waves
-constexpr int LWT = 4;        // leaf width
+constexpr int LWMAX = 8;      // largest leaf width (LDS sizing)
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
 constexpr int LIS = CT + 1;   // LDS stride of L^{-1}
 
@@ -319,7 +319,7 @@ struct PanelBufs {
   PanelSmem* ps;
 };
 
-template <typename T, int QA, int QC>
+template <typename T, int QA, int QC, int LWT>
 __device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, const PanelBufs<T>& pb,
                              DeviceStatus* status, int elem) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -566,26 +566,24 @@ template <typename T>
 struct CondenseSmem {
   static constexpr int GEMM = 2 * (KC * (256 + 1 + 64 + 2));   // elements, both tile shapes
   static size_t bytes(int n) {
-    return sizeof(T) * (GEMM + CT * LIS + CT * LWT + LWT * CT + 4 * LWT + LWT * LWT) + sizeof(PanelSmem) + 16 +
-           sizeof(int) * n;
+    return sizeof(T) * (GEMM + CT * LIS + CT * LWMAX + LWMAX * CT + 4 * LWMAX + LWMAX * LWMAX) +
+           sizeof(PanelSmem) + 16 + sizeof(int) * n;
   }
 };
 
-template <typename T, int QA, int QC>
-__global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
+template <typename T, int QA, int QC, int LW>
+__device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
   typedef Mfma<T> MF;
-  const int e = blockIdx.x;
   const int tid = threadIdx.x;
   const int n = a.n, t = a.t, N = n + t;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sg = reinterpret_cast<T*>(smem_raw);
   PanelBufs<T> pb;
   pb.Linv = sg + CondenseSmem<T>::GEMM;
   pb.Xu = pb.Linv + CT * LIS;
-  pb.Lb = pb.Xu + CT * LWT;
-  pb.prow = pb.Lb + LWT * CT;
-  pb.krow = pb.prow + 2 * LWT;
-  pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * LWT + LWT * LWT);
+  pb.Lb = pb.Xu + CT * LWMAX;
+  pb.prow = pb.Lb + LWMAX * CT;
+  pb.krow = pb.prow + 2 * LWMAX;
+  pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * LWMAX + LWMAX * LWMAX);
   int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
 
   Elem<T> el;
@@ -616,7 +614,7 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
     }
     sync_global();
     // 2. factor the panel, growing L_pp^{-1}
-    panel_factor<T, QA, QC>(el, sperm, c0, c1, pb, a.status, e);
+    panel_factor<T, QA, QC, LW>(el, sperm, c0, c1, pb, a.status, e);
     // the leaves write L_pp^{-1} on and below the diagonal of each 8-row
     // strip only; the triangular solve below reads whole 16 x 16 diagonal
     // blocks, so clear the strictly upper part (and the padding of a
@@ -672,25 +670,84 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
     }
   }
   for (int i = tid; i < n; i += NT) a.perm[(size_t)e * n + i] = sperm[i];
+  __syncthreads();  // LDS is reused by the next element of a persistent workgroup
 }
 
-template <typename T, int QA, int QC>
-static hipError_t launch_condense(const CondenseArgs<T>& a, hipStream_t s) {
+// One element per workgroup.
+template <typename T, int QA, int QC, int LW>
+__global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  condense_one<T, QA, QC, LW>(a, blockIdx.x, smem_raw);
+}
+
+// Persistent form over a work list of (segment, element) items whose
+// segments share (n, t): workgroup w takes items w, w + grid, ... in order.
+template <typename T, int QA, int QC, int LW>
+__global__ __launch_bounds__(NT) void condense_batched_kernel(const CondenseArgs<T>* segs, const int2* items,
+                                                              int n_items) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int2 w = items[it];
+    condense_one<T, QA, QC, LW>(segs[w.x], w.y, smem_raw);
+  }
+}
+
+// Leaf width chosen per local size n (set by the autotuner; default 4).
+struct LeafChoice {
+  int n, lw;
+};
+static LeafChoice g_leaf_choice[16];
+static int g_leaf_choices = 0;
+
+static int leaf_width_for(int n) {
+  for (int i = 0; i < g_leaf_choices; ++i)
+    if (g_leaf_choice[i].n == n) return g_leaf_choice[i].lw;
+  return 4;
+}
+
+template <typename T, int QA, int QC, int LW>
+static hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
+                                     int n_items, int grid, hipStream_t s) {
   const size_t smem = CondenseSmem<T>::bytes(a.n);
-  auto kern = condense_kernel<T, QA, QC>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
+  if (!segs) {
+    auto kern = condense_kernel<T, QA, QC, LW>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
+  } else {
+    auto kern = condense_batched_kernel<T, QA, QC, LW>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    // grid = resident workgroups per CU x CUs (argument `grid` is the CU count)
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, smem) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    grid = std::min(n_items, per_cu * grid);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), smem, s, segs, items, n_items);
+  }
   return hipGetLastError();
 }
 
+template <typename T, int QA, int QC>
+static hipError_t launch_condense(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
+                                  int n_items, int grid, hipStream_t s) {
+  if constexpr (QA <= 3) {
+    if (leaf_width_for(a.n) == 8) return launch_condense_lw<T, QA, QC, 8>(a, segs, items, n_items, grid, s);
+  }
+  return launch_condense_lw<T, QA, QC, 4>(a, segs, items, n_items, grid, s);
+}
+
 template <typename T>
-static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s) {
+static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, const CondenseArgs<T>* segs = nullptr,
+                                    const int2* items = nullptr, int n_items = 0, int grid = 0) {
   const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
-  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, s);
-  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, s);
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, segs, items, n_items, grid, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, segs, items, n_items, grid, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, segs, items, n_items, grid, s);
   return hipErrorInvalidValue;
 }
 
@@ -748,6 +805,8 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
 
 using namespace iedg;
 
+extern "C" void iedg_batch_destroy(iedg_batch b);
+
 extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local, int32_t n_trace_elem,
                                      iedg_prec prec, const double* A, const double* B, const double* C,
                                      const double* D, const double* F, void* LU, int32_t* perm, void* U12,
@@ -802,5 +861,107 @@ extern "C" iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense_rhs: precision");
   }
   IEDG_LAUNCH_CHECK(ctx, "condense_rhs launch");
+  return IEDG_OK;
+}
+
+// ---- batched condensation ---------------------------------------------------
+struct iedg_batch_s {
+  iedg_context ctx = nullptr;
+  int n = 0, t = 0, n_items = 0, grid = 0;
+  iedg_prec prec = IEDG_F64;
+  void* d_segs = nullptr;   // CondenseArgs<T>[n_seg]
+  int2* d_items = nullptr;  // (segment, element) work list
+  CondenseArgs<double> proto64{};
+  CondenseArgs<float> proto32{};
+};
+
+extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
+                                         int32_t n_local, int32_t n_trace_elem, iedg_prec prec, iedg_batch* out) {
+  if (!ctx || !out || n_seg <= 0 || !segs || n_local <= 0 || n_trace_elem <= 0)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: bad arguments");
+  if ((n_local & 3) || (n_trace_elem & 1) || n_local > 5 * NT || n_trace_elem > 2 * NT)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: n=%d t=%d", n_local, n_trace_elem);
+  if (prec != IEDG_F64 && prec != IEDG_F32) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: precision");
+  *out = nullptr;
+  std::vector<int2> items;
+  std::vector<CondenseArgs<double>> a64;
+  std::vector<CondenseArgs<float>> a32;
+  // items interleave the segments so that concurrently running workgroups
+  // work on different meshes' memory
+  int maxE = 0;
+  for (int s = 0; s < n_seg; ++s) {
+    const iedg_condense_segment& g = segs[s];
+    if (g.n_elem < 0 || (g.n_elem > 0 && (!g.A || !g.B || !g.C || !g.D || !g.LU || !g.perm || !g.U12 || !g.L21 || !g.Ke)))
+      return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d incomplete", s);
+    if (g.F && (!g.w || !g.r)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d F without w, r", s);
+    maxE = std::max(maxE, (int)g.n_elem);
+    a64.push_back(CondenseArgs<double>{g.n_elem, n_local, n_trace_elem, g.A, g.B, g.C, g.D, g.F, (double*)g.LU,
+                                       (double*)g.U12, (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r,
+                                       ctx->d_status});
+    a32.push_back(CondenseArgs<float>{g.n_elem, n_local, n_trace_elem, g.A, g.B, g.C, g.D, g.F, (float*)g.LU,
+                                      (float*)g.U12, (float*)g.L21, (float*)g.Ke, g.perm, g.w, g.r,
+                                      ctx->d_status});
+  }
+  for (int e = 0; e < maxE; ++e)
+    for (int s = 0; s < n_seg; ++s)
+      if (e < segs[s].n_elem) items.push_back(make_int2(s, e));
+  auto* b = new iedg_batch_s();
+  b->ctx = ctx;
+  b->n = n_local;
+  b->t = n_trace_elem;
+  b->prec = prec;
+  b->n_items = (int)items.size();
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  b->grid = ncu;  // scaled by the kernel's occupancy at launch
+  const size_t seg_bytes = prec == IEDG_F64 ? a64.size() * sizeof(a64[0]) : a32.size() * sizeof(a32[0]);
+  hipError_t e = hipMalloc(&b->d_segs, seg_bytes);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_items), std::max<size_t>(1, items.size()) * sizeof(int2));
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_segs, prec == IEDG_F64 ? (const void*)a64.data() : (const void*)a32.data(), seg_bytes,
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    iedg_batch_destroy(b);
+    return hip_check(ctx, e, "batch_create upload");
+  }
+  b->proto64 = a64[0];
+  b->proto32 = a32[0];
+  *out = b;
+  return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch b, hipStream_t stream) {
+  if (!ctx || !b) return IEDG_ERR_INVALID_ARG;
+  if (b->n_items == 0) return IEDG_OK;
+  hipError_t err;
+  if (b->prec == IEDG_F64)
+    err = dispatch_condense<double>(b->proto64, stream, (const CondenseArgs<double>*)b->d_segs, b->d_items,
+                                    b->n_items, b->grid);
+  else
+    err = dispatch_condense<float>(b->proto32, stream, (const CondenseArgs<float>*)b->d_segs, b->d_items,
+                                   b->n_items, b->grid);
+  if (err != hipSuccess) return hip_check(ctx, err, "condense_batched launch");
+  return IEDG_OK;
+}
+
+extern "C" void iedg_batch_destroy(iedg_batch b) {
+  if (!b) return;
+  if (b->d_segs) hipFree(b->d_segs);
+  if (b->d_items) hipFree(b->d_items);
+  delete b;
+}
+
+extern "C" iedg_status iedg_set_leaf_width(iedg_context ctx, int32_t n_local, int32_t leaf_width) {
+  if (!ctx || n_local <= 0 || (leaf_width != 4 && leaf_width != 8))
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "set_leaf_width: leaf width must be 4 or 8");
+  for (int i = 0; i < g_leaf_choices; ++i)
+    if (g_leaf_choice[i].n == n_local) {
+      g_leaf_choice[i].lw = leaf_width;
+      return IEDG_OK;
+    }
+  if (g_leaf_choices >= 16) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "set_leaf_width: table full");
+  g_leaf_choice[g_leaf_choices++] = LeafChoice{n_local, leaf_width};
   return IEDG_OK;
 }

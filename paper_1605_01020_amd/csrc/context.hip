@@ -284,6 +284,11 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
   if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_l, lslots);
   if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_uptr, uptr);
   if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_upd, upd);
+  if (st == IEDG_OK) {
+    const size_t rw = (size_t)E * m->t + 2 * (size_t)E + 2 * (size_t)NF;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->d_rwork), rw * sizeof(double));
+    if (e != hipSuccess) st = set_error(ctx, IEDG_ERR_OOM, "mesh residual scratch: %s", hipGetErrorString(e));
+  }
   if (st != IEDG_OK) {
     iedg_mesh_destroy(m);
     return st;
@@ -299,6 +304,7 @@ void iedg_mesh_destroy(iedg_mesh m) {
                      m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd};
   for (int32_t* p : ptrs)
     if (p) hipFree(p);
+  if (m->d_rwork) hipFree(m->d_rwork);
   delete m;
 }
 

@@ -11,9 +11,9 @@
 namespace iedg {
 
 iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x,
-                        const double* rhs, double* y, int mode, hipStream_t stream);
+                        const double* rhs, double* y, int mode, hipStream_t stream, const int* skip);
 iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
-                              double* y, hipStream_t stream);
+                              double* y, hipStream_t stream, const int* skip);
 
 constexpr int KTHR = 256;
 constexpr int KPER = 8;                 // values per thread per chunk
@@ -23,8 +23,9 @@ constexpr int MAXV = 256;               // max Krylov vectors per cycle + 2
 // partial[c * ld + k] = sum over chunk c of V_k . w   (k < nv), and, when
 // self >= 0, partial[c * ld + self] = w . w
 __global__ __launch_bounds__(KTHR) void dots_kernel(const double* V, int64_t ldv, int nv, const double* w,
-                                                    int64_t N, double* partial, int ld, int self) {
+                                                    int64_t N, double* partial, int ld, int self, const int* skip) {
   __shared__ double red[KTHR / 64];
+  if (skip && *skip) return;
   const int c = blockIdx.x;
   const int64_t base = (int64_t)c * KCH;
   double wv[KPER];
@@ -61,9 +62,10 @@ __global__ __launch_bounds__(KTHR) void dots_kernel(const double* V, int64_t ldv
 __global__ __launch_bounds__(KTHR) void cgs_update_kernel(const double* V, int64_t ldv, int nv, double* w,
                                                           int64_t N, const double* partial_in, int nb, int ld_in,
                                                           double* hcol, int accumulate, double* partial_out,
-                                                          int ld_out, int next_dots) {
+                                                          int ld_out, int next_dots, const int* skip) {
   __shared__ double h[MAXV];
   __shared__ double red[KTHR / 64];
+  if (skip && *skip) return;
   const int c = blockIdx.x;
   for (int k = threadIdx.x; k < nv; k += KTHR) {
     double s = 0.0;
@@ -122,7 +124,13 @@ struct GmresScal {
   double wn0;       // ||w|| before orthogonalisation
   double inv_scale; // 1 / value used by scale_kernel
   double norm;      // a norm requested by the host
-  double pad[3];
+  double nR;        // ||R|| (device-driven cycle)
+  double inner_tol; // inner stopping threshold (device-driven cycle)
+  double rho;       // true relative residual at the end of the cycle
+  int done;         // inner loop finished: later Arnoldi kernels return at once
+  int k;            // Arnoldi steps taken in the cycle
+  int converged;
+  int pad;
 };
 
 // Reduce nb partial sums -> sqrt, fixed order (one thread).
@@ -136,8 +144,9 @@ __device__ inline double reduce_sqrt(const double* partial, int nb, int ld, int 
 // column j, form the new rotation and update g.  One thread.
 __global__ void arnoldi_finish_kernel(const double* partial_norm, int nb, const double* partial_w0, int ld_w0,
                                       int idx_w0, double* H, int ldh, int j, double* cs, double* sn, double* g,
-                                      GmresScal* sc) {
+                                      GmresScal* sc, int device_control, int steps) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (device_control && sc->done) return;
   const double hn = reduce_sqrt(partial_norm, nb, 1, 0);
   const double wn0 = reduce_sqrt(partial_w0, nb, ld_w0, idx_w0);
   double* hc = H + (int64_t)j * ldh;
@@ -165,6 +174,10 @@ __global__ void arnoldi_finish_kernel(const double* partial_norm, int nb, const 
   sc->hn = hn;
   sc->wn0 = wn0;
   sc->inv_scale = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (device_control) {
+    sc->k = j + 1;
+    if (!(sc->est > sc->inner_tol) || hn <= 1e-14 * wn0 || j + 1 >= steps) sc->done = 1;
+  }
 }
 
 // sc->norm = sqrt(sum of partials); sc->inv_scale = 1 / norm; optionally g = (norm, 0, ...)
@@ -180,9 +193,36 @@ __global__ void norm_finish_kernel(const double* partial, int nb, int ld, int id
   }
 }
 
-__global__ void scale_kernel(double* v, int64_t N, const GmresScal* sc) {
+__global__ void scale_kernel(double* v, int64_t N, const GmresScal* sc, const int* skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) v[i] *= sc->inv_scale;
+}
+
+// dst = src * inv_scale (device-driven cycle: v0 = M^{-1} R / ||M^{-1} R||)
+__global__ void scale_copy_kernel(double* dst, const double* src, int64_t N, const GmresScal* sc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) dst[i] = src[i] * sc->inv_scale;
+}
+
+// Device-driven cycle bookkeeping after a norm was reduced into sc->norm.
+//   mode 0: norm = ||R||          -> nR, reset flags (done when R = 0)
+//   mode 1: norm = ||M^{-1} R||   -> inner threshold
+//   mode 2: norm = ||R - K x||    -> rho, converged
+__global__ void gmres_dev_set_kernel(GmresScal* sc, int mode, double rtol, double inner_factor) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (mode == 0) {
+    sc->nR = sc->norm;
+    sc->k = 0;
+    sc->converged = 0;
+    sc->done = sc->norm == 0.0 ? 1 : 0;
+    sc->rho = 0.0;
+  } else if (mode == 1) {
+    sc->inner_tol = inner_factor * rtol * sc->norm;
+  } else {
+    sc->rho = sc->nR > 0.0 ? sc->norm / sc->nR : 0.0;
+    sc->converged = sc->rho <= rtol ? 1 : 0;
+  }
 }
 
 __global__ void fill_kernel(double* v, int64_t N, double val) {
@@ -196,8 +236,10 @@ __global__ void copy_kernel(double* dst, const double* src, int64_t N) {
 }
 
 // Back substitution H(0:k, 0:k) y = g(0:k), upper triangular.  One thread.
-__global__ void hsolve_kernel(const double* H, int ldh, const double* g, int k, double* y) {
+// When sc is given, k is the device-side step count.
+__global__ void hsolve_kernel(const double* H, int ldh, const double* g, int k, double* y, const GmresScal* sc) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (sc) k = sc->k;
   for (int i = k - 1; i >= 0; --i) {
     double s = g[i];
     for (int j = i + 1; j < k; ++j) s -= H[(int64_t)j * ldh + i] * y[j];
@@ -206,9 +248,11 @@ __global__ void hsolve_kernel(const double* H, int ldh, const double* g, int k, 
 }
 
 // x += sum_{k < nv} y_k V_k
-__global__ void multi_axpy_kernel(double* x, const double* V, int64_t ldv, int nv, const double* y, int64_t N) {
+__global__ void multi_axpy_kernel(double* x, const double* V, int64_t ldv, int nv, const double* y, int64_t N,
+                                  const GmresScal* sc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
+  if (sc) nv = sc->k;
   double s = x[i];
   for (int k = 0; k < nv; ++k) s += y[k] * V[(int64_t)k * ldv + i];
   x[i] = s;
@@ -265,13 +309,13 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_p
     return IEDG_OK;
   };
   auto precond = [&](const double* in, double* out) -> iedg_status {
-    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream);
+    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream, nullptr);
     hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, out, in, N);
     return IEDG_OK;
   };
   // norm of a vector into SC->norm (and SC->inv_scale); optional g init
   auto vnorm = [&](const double* v, double* ginit) -> iedg_status {
-    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, v, ldv, 0, v, N, P3, 1, 0);
+    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, v, ldv, 0, v, N, P3, 1, 0, nullptr);
     hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, ginit, m + 1);
     return readback();
   };
@@ -297,7 +341,7 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_p
     if (first) {
       hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, tmp, R, N);
     } else {
-      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream)) != IEDG_OK) return st;
+      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream, nullptr)) != IEDG_OK) return st;
     }
     if ((st = vnorm(tmp, nullptr)) != IEDG_OK) return st;
     rho = hsc->norm / nR;
@@ -309,26 +353,26 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_p
     // v0 = M^{-1} r / ||M^{-1} r||,  g = (beta, 0, ...)
     if ((st = precond(tmp, V)) != IEDG_OK) return st;
     if ((st = vnorm(V, G)) != IEDG_OK) return st;
-    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, N, SC);
+    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, N, SC, nullptr);
     int k = 0;
     for (int j = 0; j < m; ++j) {
       double* vj = V + (int64_t)j * ldv;
       double* w = V + (int64_t)(j + 1) * ldv;
-      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream)) != IEDG_OK) return st;
+      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream, nullptr)) != IEDG_OK) return st;
       if ((st = precond(tmp, w)) != IEDG_OK) return st;
       const int nv = j + 1;
       double* hcol = H + (int64_t)j * (m + 1);
       // pass 1 dots (+ ||w||^2 before orthogonalisation at index nv)
-      hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv);
+      hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv, nullptr);
       // pass 1 update + pass 2 dots
       hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, nb, ldp, hcol, 0,
-                         P2, ldp, 1);
+                         P2, ldp, 1, nullptr);
       // pass 2 update + ||w||^2
       hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P2, nb, ldp, hcol, 1,
-                         P3, 1, 0);
+                         P3, 1, 0, nullptr);
       hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, P1, ldp, nv, H, m + 1, j, CS,
-                         SN, G, SC);
-      hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, SC);
+                         SN, G, SC, 0, 0);
+      hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, SC, nullptr);
       IEDG_LAUNCH_CHECK(ctx, "arnoldi launch");
       if ((st = readback()) != IEDG_OK) return st;
       inf.iters++;
@@ -337,8 +381,8 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_p
       if (!std::isfinite(hsc->est)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: Arnoldi produced non-finite values");
       if (hsc->est <= inner_tol || breakdown || inf.iters >= opts->max_iters) break;
     }
-    hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, H, m + 1, G, k, Y);
-    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, k, Y, N);
+    hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, H, m + 1, G, k, Y, nullptr);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, k, Y, N, nullptr);
     IEDG_LAUNCH_CHECK(ctx, "gmres update launch");
   }
   inf.rel_resid = rho;
@@ -346,5 +390,111 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_p
   if (!inf.converged)
     return set_error(ctx, IEDG_ERR_NOT_CONVERGED, "gmres: %d iterations, relative residual %.3e > %.3e", inf.iters, rho,
                      opts->rtol);
+  return IEDG_OK;
+}
+
+// ---- capturable GMRES cycle ------------------------------------------------
+struct iedg_gmres_state_s {
+  iedg_mesh mesh = nullptr;
+  int steps = 0, nb = 0, ldp = 0;
+  int64_t N = 0, ldv = 0;
+  double* buf = nullptr;
+  double *V, *tmp, *P1, *P2, *P3, *H, *CS, *SN, *G, *Y;
+  GmresScal* SC;
+};
+
+extern "C" iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
+                                               iedg_gmres_state* out) {
+  if (!ctx || !mesh || !out || steps < 1 || steps > MAXV - 2)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres_state_create: steps %d", steps);
+  auto* st = new iedg_gmres_state_s();
+  st->mesh = mesh;
+  st->steps = steps;
+  st->N = mesh->n_trace;
+  st->nb = (int)((st->N + KCH - 1) / KCH);
+  st->ldp = steps + 2;
+  st->ldv = (st->N + 63) & ~int64_t(63);
+  size_t off = 0;
+  auto take = [&](size_t count) { size_t o = off; off += (count + 63) & ~size_t(63); return o; };
+  const int m = steps;
+  const size_t oV = take((size_t)(m + 1) * st->ldv), oT = take(st->ldv), oP1 = take((size_t)st->nb * st->ldp),
+               oP2 = take((size_t)st->nb * st->ldp), oP3 = take((size_t)st->nb), oH = take((size_t)(m + 1) * m),
+               oCS = take(m), oSN = take(m), oG = take(m + 1), oY = take(m), oSC = take(sizeof(GmresScal) / 8 + 1);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&st->buf), off * sizeof(double));
+  if (e != hipSuccess) {
+    delete st;
+    return set_error(ctx, IEDG_ERR_OOM, "gmres_state_create: %zu bytes", off * sizeof(double));
+  }
+  double* W = st->buf;
+  st->V = W + oV; st->tmp = W + oT; st->P1 = W + oP1; st->P2 = W + oP2; st->P3 = W + oP3; st->H = W + oH;
+  st->CS = W + oCS; st->SN = W + oSN; st->G = W + oG; st->Y = W + oY;
+  st->SC = reinterpret_cast<GmresScal*>(W + oSC);
+  *out = st;
+  return IEDG_OK;
+}
+
+extern "C" void iedg_gmres_state_destroy(iedg_gmres_state st) {
+  if (!st) return;
+  if (st->buf) hipFree(st->buf);
+  delete st;
+}
+
+extern "C" iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st, iedg_prec kprec,
+                                          const void* Kbsr, iedg_prec mprec, const void* Mbsr, const double* R,
+                                          double* x, double rtol, double inner_factor, hipStream_t stream) {
+  if (!ctx || !mesh || !st || st->mesh != mesh || !Kbsr || !Mbsr || !R || !x || !(rtol > 0.0))
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres_enqueue: bad arguments");
+  const int64_t N = st->N, ldv = st->ldv;
+  const int nb = st->nb, ldp = st->ldp, m = st->steps;
+  double *V = st->V, *tmp = st->tmp, *P1 = st->P1, *P2 = st->P2, *P3 = st->P3, *H = st->H;
+  GmresScal* SC = st->SC;
+  const int* done = &SC->done;
+  iedg_status s;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, N, 0.0);
+  // ||R||
+  hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, R, ldv, 0, R, N, P3, 1, 0, nullptr);
+  hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, nullptr, m + 1);
+  hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 0, rtol, inner_factor);
+  // v0 = M^{-1} R / ||M^{-1} R||, g = (beta, 0, ...)
+  if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, R, tmp, stream, done)) != IEDG_OK) return s;
+  hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, tmp, ldv, 0, tmp, N, P3, 1, 0, done);
+  hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, st->G, m + 1);
+  hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 1, rtol, inner_factor);
+  hipLaunchKernelGGL(scale_copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, tmp, N, SC);
+  for (int j = 0; j < m; ++j) {
+    double* vj = V + (int64_t)j * ldv;
+    double* w = V + (int64_t)(j + 1) * ldv;
+    if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream, done)) != IEDG_OK) return s;
+    if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, tmp, w, stream, done)) != IEDG_OK) return s;
+    const int nv = j + 1;
+    double* hcol = H + (int64_t)j * (m + 1);
+    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv, done);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, nb, ldp, hcol, 0, P2,
+                       ldp, 1, done);
+    hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P2, nb, ldp, hcol, 1, P3,
+                       1, 0, done);
+    hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, P1, ldp, nv, H, m + 1, j, st->CS,
+                       st->SN, st->G, SC, 1, m);
+    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, SC, done);
+  }
+  hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, H, m + 1, st->G, 0, st->Y, SC);
+  hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, 0, st->Y, N, SC);
+  // true residual
+  if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream, nullptr)) != IEDG_OK) return s;
+  hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, tmp, ldv, 0, tmp, N, P3, 1, 0, nullptr);
+  hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, nullptr, m + 1);
+  hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 2, rtol, inner_factor);
+  IEDG_LAUNCH_CHECK(ctx, "gmres_enqueue launch");
+  return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_gmres_state_read(iedg_context ctx, iedg_gmres_state st, iedg_gmres_info* info) {
+  if (!ctx || !st || !info) return IEDG_ERR_INVALID_ARG;
+  GmresScal h;
+  IEDG_HIP(ctx, hipMemcpy(&h, st->SC, sizeof(h), hipMemcpyDeviceToHost));
+  info->iters = h.k;
+  info->cycles = 1;
+  info->converged = h.converged;
+  info->rel_resid = h.rho;
   return IEDG_OK;
 }

@@ -179,11 +179,8 @@ extern "C" iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int3
   if (!ctx || !mesh || !A || !B || !C || !D || !F || !G || !z || !uhat || !rF || !rG || !sums || n_local <= 0)
     return IEDG_ERR_INVALID_ARG;
   const int n = n_local, t = mesh->t, b = mesh->b, E = mesh->n_elem, NF = mesh->n_face;
-  // scratch: q [E][t], partials 2E + 2NF
-  const size_t need = sizeof(double) * ((size_t)E * t + 2 * (size_t)E + 2 * (size_t)NF) + 1024;
-  iedg_status st = ensure_work(ctx, need);
-  if (st != IEDG_OK) return st;
-  double* q = static_cast<double*>(ctx->work);
+  // mesh-owned scratch: q [E][t], partials 2E + 2NF
+  double* q = mesh->d_rwork;
   double* prf = q + (size_t)E * t;
   double* pf = prf + E;
   double* prg = pf + E;

@@ -31,4 +31,8 @@ struct iedg_mesh_s {
   int32_t* d_ilu_l = nullptr;       // [n_lslots][2]: slot (i,k), diag slot of k
   int32_t* d_ilu_uptr = nullptr;    // [n_lslots + 1] into ilu_upd
   int32_t* d_ilu_upd = nullptr;     // [n_updates][2]: slot (k,j), slot (i,j)
+
+  // scratch of the FP64 residual (q [E][t], partial sums 2E + 2 n_face),
+  // owned by the mesh so that residual launches never allocate
+  double* d_rwork = nullptr;
 };

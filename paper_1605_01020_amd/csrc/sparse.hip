@@ -104,8 +104,9 @@ __device__ inline void group_reduce(double* red, int b, int G, int g, int rr, do
 template <typename T>
 __global__ __launch_bounds__(STHR) void spmv_kernel(int b, const int32_t* row_face, const int32_t* row_ptr,
                                                     const int32_t* col_face, const T* K, const double* x,
-                                                    const double* rhs, double* y, int mode) {
+                                                    const double* rhs, double* y, int mode, const int* skip) {
   __shared__ double red[STHR + 128];
+  if (skip && *skip) return;
   const int i = blockIdx.x;
   const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
   const double v = block_row_sum<T>(b, K, col_face, row_ptr[i], row_ptr[i + 1], x, g, G, rr);
@@ -124,8 +125,9 @@ template <typename T>
 __global__ __launch_bounds__(STHR) void sweep_kernel(int b, const int32_t* rows, const int32_t* row_face,
                                                      const int32_t* row_ptr, const int32_t* diag_slot,
                                                      const int32_t* col_face, const T* M, const double* x,
-                                                     double* y, int upper) {
+                                                     double* y, int upper, const int* skip) {
   __shared__ double red[STHR + 128];
+  if (skip && *skip) return;
   const int i = rows[blockIdx.x];
   const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
   const int ds = diag_slot[i];
@@ -444,20 +446,20 @@ using namespace iedg;
 namespace iedg {
 
 iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x,
-                        const double* rhs, double* y, int mode, hipStream_t stream) {
+                        const double* rhs, double* y, int mode, hipStream_t stream, const int* skip) {
   if (kprec == IEDG_F64)
     hipLaunchKernelGGL(spmv_kernel<double>, dim3(m->n_face), dim3(STHR), 0, stream, m->b, m->d_row_face,
-                       m->d_row_ptr, m->d_col_face, (const double*)K, x, rhs, y, mode);
+                       m->d_row_ptr, m->d_col_face, (const double*)K, x, rhs, y, mode, skip);
   else
     hipLaunchKernelGGL(spmv_kernel<float>, dim3(m->n_face), dim3(STHR), 0, stream, m->b, m->d_row_face,
-                       m->d_row_ptr, m->d_col_face, (const float*)K, x, rhs, y, mode);
+                       m->d_row_ptr, m->d_col_face, (const float*)K, x, rhs, y, mode, skip);
   IEDG_LAUNCH_CHECK(ctx, "spmv launch");
   return IEDG_OK;
 }
 
 // y = M^{-1} x : forward sweep over levels, then backward sweep in reverse.
 iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
-                              double* y, hipStream_t stream) {
+                              double* y, hipStream_t stream, const int* skip) {
   for (int dir = 0; dir < 2; ++dir) {
     for (int li = 0; li < m->n_levels; ++li) {
       const int l = dir == 0 ? li : m->n_levels - 1 - li;
@@ -466,11 +468,11 @@ iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, co
       if (mprec == IEDG_F64)
         hipLaunchKernelGGL(sweep_kernel<double>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
                            m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const double*)M, src, y,
-                           dir);
+                           dir, skip);
       else
         hipLaunchKernelGGL(sweep_kernel<float>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
                            m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const float*)M, src, y,
-                           dir);
+                           dir, skip);
     }
   }
   IEDG_LAUNCH_CHECK(ctx, "ilu0 sweep launch");
@@ -557,13 +559,13 @@ iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh m, iedg_prec prec, cons
 iedg_status iedg_spmv(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x, double* y,
                       hipStream_t stream) {
   if (!ctx || !m || !K || !x || !y) return IEDG_ERR_INVALID_ARG;
-  return spmv_launch(ctx, m, kprec, K, x, nullptr, y, 0, stream);
+  return spmv_launch(ctx, m, kprec, K, x, nullptr, y, 0, stream, nullptr);
 }
 
 iedg_status iedg_ilu0_apply(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
                             double* y, hipStream_t stream) {
   if (!ctx || !m || !M || !x || !y) return IEDG_ERR_INVALID_ARG;
-  return ilu0_apply_launch(ctx, m, mprec, M, x, y, stream);
+  return ilu0_apply_launch(ctx, m, mprec, M, x, y, stream, nullptr);
 }
 
 }  // extern "C"

@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=4.0)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="first run a plain device copy of this many GiB (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,6 +183,17 @@ def main():
               "multi-GPU runs (RAS across subdomains) are not part of this build.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe_gib > 0:
+        import torch
+        nbytes = int(args.copy_probe_gib * 2 ** 30)
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log(f"copy probe: 3 copies of {nbytes} bytes")
+        del src, dst
+        torch.cuda.empty_cache()
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serving":

@@ -140,8 +140,9 @@ iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32_t n_local,
                               hipStream_t stream);
 
 /* Batched condensation (section 2.2.1, eq. LS) of several meshes whose
- * elements share (n, t): one persistent launch over a work list of
- * (segment, element) items, each item exactly as iedg_condense.  The plan
+ * elements share (n, t): one launch over a work list of (segment,
+ * element) items that interleaves the segments, each item computed exactly
+ * as iedg_condense computes it (bitwise the same outputs).  The plan
  * copies the segment table to the device once; iedg_condense_batched only
  * launches (it can be captured in a HIP graph).  Segment pointers must stay
  * valid for the plan's lifetime. */
@@ -161,9 +162,14 @@ iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_conden
                               iedg_batch* out);
 iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch batch, hipStream_t stream);
 void iedg_batch_destroy(iedg_batch batch);
-/* Tuning of the condensation kernel: panel leaf width (4 or 8 columns)
- * used for elements with n local dofs (process-wide; default 4). */
-iedg_status iedg_set_leaf_width(iedg_context ctx, int32_t n_local, int32_t leaf_width);
+/* Tuning of the condensation kernel: width of the register-resident
+ * sub-panels of the panel factorisation (8 or 16 columns) for `prec`
+ * (IEDG_F64 or IEDG_F32) and elements with n local dofs.  Process-wide; a
+ * width that the register file cannot hold for that case spills to scratch
+ * memory (slower, same result).  Untuned: 16 for FP32 with n <= 1536 and
+ * t <= 512 and for FP64 with n <= 512 and t <= 512, else 8. */
+iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int32_t n_local,
+                                int32_t leaf_width);
 
 /* ---- a2: assembly of K and R (section 2.2.1, eq. LS) ------------------ */
 /* Kbsr = sum_e P_e^T Ke_e P_e in the BSR layout of `mesh` (storage in

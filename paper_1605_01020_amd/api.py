@@ -205,8 +205,9 @@ class CondenseBatch:
             pass
 
 
-def set_leaf_width(ctx, n_local, leaf_width):
-    ctx.check(ctx.L.iedg_set_leaf_width(ctx.h, int(n_local), int(leaf_width)))
+def set_leaf_width(ctx, n_local, leaf_width, prec=F32):
+    """Sub-panel width (8 or 16) of the condensation kernel for (prec, n)."""
+    ctx.check(ctx.L.iedg_set_leaf_width(ctx.h, int(prec), int(n_local), int(leaf_width)))
 
 
 class GmresState:

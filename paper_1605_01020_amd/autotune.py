@@ -1,7 +1,7 @@
-"""Measured choice of the condensation kernel's panel leaf width.
+"""Measured choice of the condensation kernel's sub-panel width.
 
-The panel factorisation of the condensation kernel works on leaves of 4 or
-8 columns (8 is built for n <= 1536).  For each element size the tuner
+The panel factorisation of the condensation kernel keeps sub-panels of 8
+or 16 columns in registers.  For each precision and element size the tuner
 times both on a device-generated sample of elements and keeps the faster;
 the table is stored as tuning.json beside this file and applied with
 iedg_set_leaf_width.
@@ -14,7 +14,7 @@ import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(_HERE, "tuning.json")
-LEAF_CHOICES = {2: (4, 8), 3: (4, 8), 4: (4,)}
+LEAF_CHOICES = (8, 16)
 
 
 def _time_condense(ctx, spec, d, prec, reps):
@@ -34,28 +34,31 @@ def _time_condense(ctx, spec, d, prec, reps):
     return min(ts)
 
 
-def tune(ctx, ps=(2, 3, 4), n_elem=512, reps=3, seed=1605010203, log=print):
+def tune(ctx, ps=(2, 3, 4), precs=None, n_elem=512, reps=3, seed=1605010203, log=print):
     import torch
     from . import api
-    from ._lib import F32
+    from ._lib import F32, F64
     from synth import ElementSpec
     import synth.device as sd
-    table = {"prec": "f32", "n_elem": n_elem, "entries": []}
+    precs = (F32, F64) if precs is None else precs
+    table = {"n_elem": n_elem, "entries": []}
     for p in ps:
         spec = ElementSpec(p)
         d = sd.gen_blocks(spec, seed, 0, n_elem, which="ABCDF")
-        best = None
-        times = {}
-        for lw in LEAF_CHOICES[p]:
-            api.set_leaf_width(ctx, spec.n, lw)
-            ms = _time_condense(ctx, spec, d, F32, reps)
-            times[lw] = ms
-            log(f"p={p} n={spec.n} leaf={lw}: {ms:.2f} ms for {n_elem} elements")
-            if best is None or ms < times[best]:
-                best = lw
-        api.set_leaf_width(ctx, spec.n, best)
-        table["entries"].append({"p": p, "n": spec.n, "leaf_width": best,
-                                 "ms": {str(k): v for k, v in times.items()}})
+        for prec in precs:
+            best = None
+            times = {}
+            for lw in LEAF_CHOICES:
+                api.set_leaf_width(ctx, spec.n, lw, prec=prec)
+                ms = _time_condense(ctx, spec, d, prec, reps)
+                times[lw] = ms
+                log(f"p={p} n={spec.n} prec={'f64' if prec == F64 else 'f32'} sub-panel {lw}: "
+                    f"{ms:.2f} ms for {n_elem} elements")
+                if best is None or ms < times[best]:
+                    best = lw
+            api.set_leaf_width(ctx, spec.n, best, prec=prec)
+            table["entries"].append({"p": p, "n": spec.n, "prec": "f64" if prec == F64 else "f32",
+                                     "leaf_width": best, "ms": {str(k): v for k, v in times.items()}})
         del d
         torch.cuda.empty_cache()
     return table
@@ -68,8 +71,9 @@ def apply_tuning(ctx, path=TUNING_PATH):
         return None
     with open(path) as f:
         table = json.load(f)
+    from ._lib import F32, F64
     for e in table.get("entries", []):
-        api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]))
+        api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]), prec=F64 if e.get("prec") == "f64" else F32)
     return table
 
 

@@ -3,9 +3,10 @@ size and polynomial degree solved together (section 2.2 for every mesh).
 
 Per memory group of meshes:
   * condensation (section 2.2.1, eq. LS) of every element of every mesh in
-    the group by ONE persistent launch per element size (n, t): the work
-    list interleaves (mesh, element) items, so small and large meshes share
-    the chip;
+    the group by ONE launch per element size (n, t): the work list
+    interleaves (mesh, element) items, so small and large meshes share the
+    chip, and the hardware dispatcher hands the next item to whichever CU
+    finishes first;
   * per mesh: assembly, BILU(0) of the low-precision trace matrix, one
     device-driven GMRES cycle (section 2.2.2, eq. LS1), local
     back-substitution, then a fixed number of FP64 refinement steps

@@ -15,10 +15,10 @@
 //   for each panel [c0, c1):
 //     1. panel column (Crout order): M[c0:, c0:c1] = in - L[c0:, :c0] U[:c0, c0:c1]
 //        -- MFMA tiles of 256 x 64 fed from double-buffered LDS k-slabs
-//     2. panel factorisation in leaves of 4 columns held in registers:
-//        each leaf first takes the updates of the panel's earlier leaves
-//        (left-looking, fused into its load), then partial pivoting with a
-//        workgroup argmax per column; the panel's L^{-1} is grown in LDS
+//     2. panel factorisation in register-resident sub-panels of 16 (or 8)
+//        columns: each sub-panel first takes the updates of the panel's
+//        earlier sub-panels (left-looking), then partial pivoting with one
+//        workgroup barrier per column; the panel's L^{-1} is grown in LDS
 //     3. panel row: U[c0:c1, c1:] = L_pp^{-1} (in - L[c0:c1, :c0] U[:c0, c1:])
 //        -- MFMA tiles of 64 x 256; the triangular solve with L_pp^{-1} is a
 //        second MFMA pass on the accumulators (each wave owns whole columns)
@@ -29,10 +29,20 @@
 
 namespace iedg {
 
+// A value the optimiser cannot trace back to the register array it came
+// from: a select between such values is never rewritten into a load through
+// a selected address (which would demote the array to scratch memory).
+template <typename T>
+__device__ __attribute__((always_inline)) inline T opaque(T v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+
 constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
 constexpr int NW = NT / 64;   // waves
-constexpr int LWMAX = 8;      // largest leaf width (LDS sizing)
+constexpr int SWMAX = 16;     // widest sub-panel (LDS sizing)
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
 constexpr int LIS = CT + 1;   // LDS stride of L^{-1}
 
@@ -56,7 +66,7 @@ struct Elem {
   double *w, *r;
   const int* sperm;
 
-  __device__ T in(int row, int col) const {
+  __device__ __attribute__((always_inline)) T in(int row, int col) const {
     if (row < n) {
       const size_t pr = (size_t)sperm[row];
       if (col < n) return (T)A[pr * n + col];
@@ -68,7 +78,7 @@ struct Elem {
     if (col < N) return (T)D[q * t + (col - n)];
     return T(0);
   }
-  __device__ T ld(int row, int col) const {
+  __device__ __attribute__((always_inline)) T ld(int row, int col) const {
     if (row < n) {
       const size_t pr = (size_t)sperm[row];
       if (col < n) return LU[pr * n + col];
@@ -80,7 +90,7 @@ struct Elem {
     if (col < N) return Ke[q * t + (col - n)];
     return (T)r[q];
   }
-  __device__ void st(int row, int col, T v) const {
+  __device__ __attribute__((always_inline)) void st(int row, int col, T v) const {
     if (row < n) {
       const size_t pr = (size_t)sperm[row];
       if (col < n) LU[pr * n + col] = v;
@@ -94,7 +104,7 @@ struct Elem {
     else r[q] = (double)v;
   }
   // L part (columns < n) of position `row`
-  __device__ const T* lrow(int row) const {
+  __device__ __attribute__((always_inline)) T* lrow(int row) const {
     return row < n ? LU + (size_t)sperm[row] * n : L21 + (size_t)(row - n) * n;
   }
 };
@@ -136,7 +146,7 @@ struct SlabLoader {
   const int* sperm;
   int K;
 
-  __device__ inline void init(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K_) {
+  __device__ __attribute__((always_inline)) inline void init(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K_) {
     const int tid = threadIdx.x;
     sperm = el.sperm;
     K = K_;
@@ -163,7 +173,7 @@ struct SlabLoader {
       else { bw[q] = el.w; }
     }
   }
-  __device__ inline void load(int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) const {
+  __device__ __attribute__((always_inline)) inline void load(int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) const {
     const int k0 = ch * KC;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
@@ -187,7 +197,7 @@ struct SlabLoader {
       vb[q] = v;
     }
   }
-  __device__ inline void store(T* stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) const {
+  __device__ __attribute__((always_inline)) inline void store(T* stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) const {
     T* As = stage;
     T* Bs = stage + KC * TL::SA;
 #pragma unroll
@@ -201,7 +211,7 @@ struct SlabLoader {
 };
 
 template <typename T, int TM, int TN>
-__device__ inline void slab_mma(const T* stage, int wr0, int wc0,
+__device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, int wr0, int wc0,
                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
   typedef Tile<T, TM, TN> TL;
   typedef Mfma<T> MF;
@@ -230,7 +240,7 @@ __device__ inline void slab_mma(const T* stage, int wr0, int wc0,
 // The slab loop is unrolled by two so that stage and buffer indices are
 // compile-time constants.
 template <typename T, int TM, int TN>
-__device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
+__device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
   typedef Tile<T, TM, TN> TL;
   typedef Mfma<T> MF;
@@ -273,7 +283,7 @@ __device__ inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, in
 
 // Visit this wave's accumulator elements as (row, col) of the tile.
 template <typename T, int TM, int TN, typename F>
-__device__ inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+__device__ __attribute__((always_inline)) inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
                                F f) {
   typedef Tile<T, TM, TN> TL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -289,7 +299,7 @@ __device__ inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Ti
 
 // acc element v = f(row, col, value) over this wave's accumulators.
 template <typename T, int TM, int TN, typename F>
-__device__ inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+__device__ __attribute__((always_inline)) inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
                                F f) {
   typedef Tile<T, TM, TN> TL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -304,275 +314,362 @@ __device__ inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Ti
 }
 
 // ---- panel factorisation -------------------------------------------------
+// The panel [c0, c1) is factored in sub-panels of SW columns.  Every thread
+// owns the same positions for the whole panel: A position p >= c0 belongs
+// to thread (p - c0) % NT, slot (p - c0) / NT; C row n + q to thread q % NT,
+// slot q / NT.  A sub-panel lives in registers while its columns are
+// factored, so a pivot column costs one workgroup barrier and no global
+// memory traffic.  Between sub-panels the update is left-looking: the U
+// rows above the sub-panel come from the panel's L^{-1} (in LDS), and each
+// thread applies the L values of its own rows (re-read from global, written
+// there by the same thread's earlier sub-panels).
+template <typename T, int QA, int QC, int SW>
+struct PanelShape {
+  static constexpr int R = QA + QC;
+  static constexpr int W = sizeof(T) / 4;  // registers per value
+  // L values per row fetched per round trip (keeps x + chunk near 128 regs)
+  static constexpr int KCH = (R * 16 * W <= 64) ? 16 : ((R * 8 * W <= 64) ? 8 : 4);
+};
+
 struct PanelSmem {
-  double red_v[2][NW];   // double-buffered by column parity
-  int red_i[2][NW];
+  double cv[2][NW];   // wave maxima, double-buffered by column parity
+  int ci[2][NW];      // their positions
 };
 
 template <typename T>
 struct PanelBufs {
   T* Linv;   // CT x LIS: L_pp^{-1} of the panel's factored columns so far
-  T* Xu;     // CT x LWT: rows [c0, cs) of the leaf columns (input / U)
-  T* Lb;     // LWT x CT: L(cs:ce, c0:ce) rows of the leaf
-  T* prow;   // 2 x LWT: pivot row of the current column (by column parity)
-  T* krow;   // 2 x LWT: displaced row
+  T* Xu;     // CT x SWMAX: rows [c0, cs) of the sub-panel (input), then scratch
+  T* Ut;     // CT x SWMAX: U rows [c0, cs) of the sub-panel
+  T* Lb;     // SWMAX x CT: L(cs:ce, c0:ce) rows of the sub-panel
+  T* cand;   // 2 x NW x SWMAX: each wave's best candidate row, by column parity
+  T* krow;   // 2 x SWMAX: row at the pivot position before the interchange
   PanelSmem* ps;
 };
 
-template <typename T, int QA, int QC, int LWT>
-__device__ void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1, const PanelBufs<T>& pb,
-                             DeviceStatus* status, int elem) {
+// Rotate every register row left by one column.
+template <typename T, int QA, int QC, int SW>
+__device__ __attribute__((always_inline)) inline void rotate_rows(T (&x)[QA][SW], T (&xc)[QC][SW]) {
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const T f = x[q][0];
+#pragma unroll
+    for (int j = 0; j + 1 < SW; ++j) x[q][j] = x[q][j + 1];
+    x[q][SW - 1] = f;
+  }
+#pragma unroll
+  for (int q = 0; q < QC; ++q) {
+    const T f = xc[q][0];
+#pragma unroll
+    for (int j = 0; j + 1 < SW; ++j) xc[q][j] = xc[q][j + 1];
+    xc[q][SW - 1] = f;
+  }
+}
+
+template <typename T, int QA, int QC, int SW>
+__device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1,
+                                                            const PanelBufs<T>& pb, DeviceStatus* status, int elem) {
+  typedef PanelShape<T, QA, QC, SW> PS;
+  constexpr int KCH = PS::KCH;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = el.n, N = el.N;
-  for (int cs = c0; cs < c1; cs += LWT) {
-    const int ce = min(cs + LWT, c1), lw = ce - cs, kp = cs - c0;  // kp: panel columns already factored
-    // (a) U rows [c0, cs) of the leaf columns: U = Linv[0:kp, 0:kp] X
-    if (kp > 0) {
-      for (int q = tid; q < kp * LWT; q += NT) {
-        const int i = q / LWT, j = q % LWT;
-        pb.Xu[i * LWT + j] = j < lw ? el.ld(c0 + i, cs + j) : T(0);
-      }
-      __syncthreads();
-      T u_val = T(0);
-      int ui = -1, uj = 0;
-      if (tid < kp * LWT) {
-        ui = tid / LWT;
-        uj = tid % LWT;
-        T s = T(0);
-        for (int k = 0; k <= ui; ++k) s += pb.Linv[ui * LIS + k] * pb.Xu[k * LWT + uj];
-        u_val = s;
-      }
-      __syncthreads();
-      if (ui >= 0) {
-        pb.Xu[ui * LWT + uj] = u_val;
-        if (uj < lw) el.st(c0 + ui, cs + uj, u_val);
-      }
-      sync_global();
-    }
-    // (b) load the leaf rows with the panel's earlier updates applied
-    // rows of A (positions cs + tid + NT q) and of C (n + tid + NT q); the L
-    // values of a row in columns [c0, cs) are contiguous: read them 8 at a
-    // time for all owned rows together so the loads overlap
-    T x[QA][LWT];
-    T xc[QC][LWT];
-    const T* lra[QA];
-    const T* lrc[QC];
+  for (int cs = c0; cs < c1; cs += SW) {
+    const int sw = min(SW, c1 - cs), kp = cs - c0;
+    // the previous sub-panel's stores are read below by other threads (rows
+    // change owners through interchanges)
+    if (kp > 0) sync_global();
+    // (1) the sub-panel columns of every owned row (Crout-updated by the
+    //     panel-column GEMM; earlier panels' interchanges via sperm)
+    //     (columns < n: LU rows for A positions, L21 rows for C rows)
+    T x[QA][SW];
+    T xc[QC][SW];
+    T* xra[QA];
+    T* xrc[QC];
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-      const int row = cs + tid + NT * q;
-      lra[q] = row < n ? el.lrow(row) + c0 : nullptr;
-#pragma unroll
-      for (int j = 0; j < LWT; ++j) x[q][j] = (row < n && j < lw) ? el.ld(row, cs + j) : T(0);
+      const int p = c0 + tid + NT * q;
+      xra[q] = p < n ? el.lrow(p) + cs : nullptr;
     }
 #pragma unroll
     for (int q = 0; q < QC; ++q) {
-      const int row = n + tid + NT * q;
-      lrc[q] = row < N ? el.lrow(row) + c0 : nullptr;
-#pragma unroll
-      for (int j = 0; j < LWT; ++j) xc[q][j] = (row < N && j < lw) ? el.ld(row, cs + j) : T(0);
+      const int r = n + tid + NT * q;
+      xrc[q] = r < N ? el.lrow(r) + cs : nullptr;
     }
-    // KB columns of L per round trip (kp is a multiple of LWT; the tail of
-    // the last group reads zeros)
-    constexpr int KB = QA <= 3 ? 16 : 4;
-    for (int k0 = 0; k0 < kp; k0 += KB) {
-      T la[QA][KB], lc[QC][KB];
+    if (sw == SW) {
 #pragma unroll
       for (int q = 0; q < QA; ++q)
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) la[q][kk] = (lra[q] && k0 + kk < kp) ? lra[q][k0 + kk] : T(0);
+        for (int j = 0; j < SW; ++j) x[q][j] = xra[q] ? xra[q][j] : T(0);
 #pragma unroll
       for (int q = 0; q < QC; ++q)
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) lc[q][kk] = (lrc[q] && k0 + kk < kp) ? lrc[q][k0 + kk] : T(0);
+        for (int j = 0; j < SW; ++j) xc[q][j] = xrc[q] ? xrc[q][j] : T(0);
+    } else {
 #pragma unroll
-      for (int kk = 0; kk < KB; ++kk) {
-        if (k0 + kk < kp) {
-          T u[LWT];
+      for (int q = 0; q < QA; ++q)
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) u[j] = pb.Xu[(k0 + kk) * LWT + j];
+        for (int j = 0; j < SW; ++j) x[q][j] = (xra[q] && j < sw) ? xra[q][j] : T(0);
 #pragma unroll
-          for (int q = 0; q < QA; ++q)
+      for (int q = 0; q < QC; ++q)
 #pragma unroll
-            for (int j = 0; j < LWT; ++j) x[q][j] -= la[q][kk] * u[j];
-#pragma unroll
-          for (int q = 0; q < QC; ++q)
-#pragma unroll
-            for (int j = 0; j < LWT; ++j) xc[q][j] -= lc[q][kk] * u[j];
-        }
-      }
+        for (int j = 0; j < SW; ++j) xc[q][j] = (xrc[q] && j < sw) ? xrc[q][j] : T(0);
     }
-    // (c) partial pivoting over positions [k, n), one column at a time.  The
-    // LDS scratch alternates by column parity, so two barriers per column
-    // suffice: a wave can only overwrite a buffer after every wave has
-    // passed the first barrier of the next column, i.e. finished reading it.
+    if (kp > 0) {
+      // (2) U rows [c0, cs): Ut = L_pp^{-1}[0:kp, 0:kp] X[c0:cs]; positions
+      //     c0 .. cs-1 are slot 0 of threads 0 .. kp-1
+      if (tid < kp) {
 #pragma unroll
-    for (int kk = 0; kk < LWT; ++kk) {
-      if (kk < lw) {
-        const int k = cs + kk, par = kk & 1;
-        double* rv = pb.ps->red_v[par];
-        int* ri = pb.ps->red_i[par];
-        T* prow = pb.prow + par * LWT;
-        T* krow = pb.krow + par * LWT;
-        double best = -1.0;
-        int bidx = INT_MAX;
+        for (int j = 0; j < SW; ++j) pb.Xu[tid * SW + j] = x[0][j];
+      }
+      __syncthreads();
+      for (int o = tid; o < kp * SW; o += NT) {
+        const int i = o / SW, j = o % SW;
+        T acc = T(0);
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * LIS + m] * pb.Xu[m * SW + j];
+        pb.Ut[o] = acc;
+      }
+      __syncthreads();
+      if (tid < kp) {
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-          const int row = cs + tid + NT * q;
-          const double v = fabs((double)x[q][kk]);
-          if (row >= k && row < n && v > best) { best = v; bidx = row; }
-        }
+        for (int j = 0; j < SW; ++j) x[0][j] = pb.Ut[tid * SW + j];
+      }
+      // (3) rows at positions >= cs and the C rows: X -= L[row, c0:cs] Ut,
+      //     KCH columns of L per round trip
+      const T* lra[QA];
+      const T* lrc[QC];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ov = __shfl_xor(best, off, kWave);
-          const int oi = __shfl_xor(bidx, off, kWave);
-          if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-        }
-        if (lane == 0) { rv[wv] = best; ri[wv] = bidx; }
-        __syncthreads();
-        best = rv[0];
-        bidx = ri[0];
+      for (int q = 0; q < QA; ++q) {
+        const int p = c0 + tid + NT * q;
+        lra[q] = (p >= cs && p < n) ? el.lrow(p) + c0 : nullptr;
+      }
 #pragma unroll
-        for (int i = 1; i < NW; ++i) {
-          const double ov = rv[i];
-          const int oi = ri[i];
-          if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-        }
-        int piv = bidx;
-        if (piv == INT_MAX || !(best > 0.0) || !isfinite(best)) {
-          if (tid == 0) latch_status(status, IEDG_ERR_SINGULAR, elem);
-          piv = k;
-        }
-        const int po = piv - cs;  // owner: thread po % NT, slot po / NT
-        if (tid == po % NT) {
+      for (int q = 0; q < QC; ++q) {
+        const int r = n + tid + NT * q;
+        lrc[q] = r < N ? el.lrow(r) + c0 : nullptr;
+      }
+      for (int k0 = 0; k0 < kp; k0 += KCH) {
+        T la[QA][KCH], lc[QC][KCH];
 #pragma unroll
-          for (int q = 0; q < QA; ++q)
-            if (q == po / NT)
+        for (int q = 0; q < QA; ++q)
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) prow[j] = x[q][j];
-        }
-        if (tid == kk) {
+          for (int kk = 0; kk < KCH; ++kk) la[q][kk] = (lra[q] && k0 + kk < kp) ? lra[q][k0 + kk] : T(0);
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) krow[j] = x[0][j];
-        }
-        __syncthreads();
-        if (piv != k && tid == po % NT) {
+        for (int q = 0; q < QC; ++q)
 #pragma unroll
-          for (int q = 0; q < QA; ++q)
-            if (q == po / NT)
+          for (int kk = 0; kk < KCH; ++kk) lc[q][kk] = (lrc[q] && k0 + kk < kp) ? lrc[q][k0 + kk] : T(0);
 #pragma unroll
-              for (int j = 0; j < LWT; ++j) x[q][j] = krow[j];
-        }
-        if (tid == kk) {
+        for (int kk = 0; kk < KCH; ++kk) {
+          if (k0 + kk < kp) {
+            const T* u = pb.Ut + (k0 + kk) * SW;
 #pragma unroll
-          for (int j = 0; j < LWT; ++j) x[0][j] = prow[j];
-        }
-        if (tid == 0) {
-          const int tmp = sperm[k];
-          sperm[k] = sperm[piv];
-          sperm[piv] = tmp;
-        }
-        T u[LWT];
+            for (int j = 0; j < SW; ++j) {
+              const T uj = u[j];
 #pragma unroll
-        for (int j = 0; j < LWT; ++j) u[j] = prow[j];
-        const T ukk = u[kk];
+              for (int q = 0; q < QA; ++q) x[q][j] -= la[q][kk] * uj;
 #pragma unroll
-        for (int q = 0; q < QA; ++q) {
-          const int row = cs + tid + NT * q;
-          if (row > k && row < n) {
-            const T l = x[q][kk] / ukk;
-            x[q][kk] = l;
-#pragma unroll
-            for (int j = kk + 1; j < LWT; ++j) x[q][j] -= l * u[j];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < QC; ++q) {
-          if (n + tid + NT * q < N) {
-            const T l = xc[q][kk] / ukk;
-            xc[q][kk] = l;
-#pragma unroll
-            for (int j = kk + 1; j < LWT; ++j) xc[q][j] -= l * u[j];
+              for (int q = 0; q < QC; ++q) xc[q][j] -= lc[q][kk] * uj;
+            }
           }
         }
       }
     }
-    // (d) write the leaf back (positions now final for rows [cs, ce))
+    // (4) partial pivoting, one column at a time, one barrier per column:
+    //     each wave posts its best candidate row and the owner of position k
+    //     posts row k, so after the barrier every thread can take the pivot
+    //     row and perform the interchange.  Buffers alternate by column
+    //     parity: a buffer is rewritten only after every wave has passed the
+    //     next column's barrier, i.e. finished reading it.
+    //     The column loop is not unrolled (it would not fit the instruction
+    //     cache): instead every register row is rotated by one after each
+    //     column, so the current column always sits in register 0 and
+    //     register j holds column kk + j (mod SW).  LDS rows use the same
+    //     rotation.
+    for (int kk = 0; kk < sw; ++kk) {
+      const int k = cs + kk, par = kk & 1;
+      T best = T(-1);
+      int bq = -1;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int p = c0 + tid + NT * q;
+        const T v = fabs(x[q][0]);
+        if (p >= k && p < n && v > best) { best = v; bq = q; }
+      }
+      const int mine = bq >= 0 ? c0 + tid + NT * bq : INT_MAX;
+      int bidx = mine;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const T ov = __shfl_xor(best, off, kWave);
+        const int oi = __shfl_xor(bidx, off, kWave);
+        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+      }
+      // (register rows are chosen with value selects, never through a
+      // pointer to a row, so that they stay in registers)
+      T* cw = pb.cand + (par * NW + wv) * SW;
+      if (mine == bidx && bidx != INT_MAX) {
+#pragma unroll
+        for (int j = 0; j < SW; ++j) {
+          T v = x[0][j];
+#pragma unroll
+          for (int q = 1; q < QA; ++q) v = (q == bq) ? opaque(x[q][j]) : v;
+          cw[j] = v;
+        }
+      }
+      if (lane == 0) { pb.ps->cv[par][wv] = (double)best; pb.ps->ci[par][wv] = bidx; }
+      const int ko = k - c0;  // owner of position k: thread ko (slot 0, ko < CT <= NT)
+      const bool own_k = tid == ko;
+      T* kr = pb.krow + par * SW;
+      if (own_k) {
+#pragma unroll
+        for (int j = 0; j < SW; ++j) kr[j] = x[0][j];
+      }
+      __syncthreads();
+      double gbest = pb.ps->cv[par][0];
+      bidx = pb.ps->ci[par][0];
+      int bw = 0;
+#pragma unroll
+      for (int i = 1; i < NW; ++i) {
+        const double ov = pb.ps->cv[par][i];
+        const int oi = pb.ps->ci[par][i];
+        if (ov > gbest || (ov == gbest && oi < bidx)) { gbest = ov; bidx = oi; bw = i; }
+      }
+      int piv = bidx;
+      const T* urow = pb.cand + (par * NW + bw) * SW;
+      if (piv == INT_MAX || !(gbest > 0.0) || !isfinite(gbest)) {
+        if (tid == 0) latch_status(status, IEDG_ERR_SINGULAR, elem);
+        piv = k;
+        urow = kr;
+      }
+      T u[SW];
+#pragma unroll
+      for (int j = 0; j < SW; ++j) u[j] = urow[j];
+      const int po = piv - c0;
+      const bool own_p = piv != k && tid == po % NT;
+      const int sp = po / NT;
+      if (own_p || own_k) {
+#pragma unroll
+        for (int j = 0; j < SW; ++j) {
+          const T kv = kr[j];
+#pragma unroll
+          for (int q = 0; q < QA; ++q) {
+            T v = (own_p && q == sp) ? kv : x[q][j];
+            x[q][j] = (own_k && q == 0) ? u[j] : v;
+          }
+        }
+      }
+      if (tid == 0 && piv != k) {
+        const int tmp = sperm[k];
+        sperm[k] = sperm[piv];
+        sperm[piv] = tmp;
+      }
+      // eliminate below the pivot: registers 1 .. sw-kk-1 are the columns
+      // right of k in this sub-panel (the others hold finished columns)
+      const T rinv = T(1) / u[0];
+      const int live = sw - kk;
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int p = c0 + tid + NT * q;
+        if (p > k && p < n) {
+          const T l = x[q][0] * rinv;
+          x[q][0] = l;
+#pragma unroll
+          for (int j = 1; j < SW; ++j)
+            if (j < live) x[q][j] -= l * u[j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QC; ++q) {
+        if (n + tid + NT * q < N) {
+          const T l = xc[q][0] * rinv;
+          xc[q][0] = l;
+#pragma unroll
+          for (int j = 1; j < SW; ++j)
+            if (j < live) xc[q][j] -= l * u[j];
+        }
+      }
+      rotate_rows<T, QA, QC, SW>(x, xc);
+    }
+    // sw rotations so far; complete a full turn
+    for (int r = sw; r < SW; ++r) rotate_rows<T, QA, QC, SW>(x, xc);
+    __syncthreads();  // final sperm of this sub-panel
+    // (5) write the sub-panel back: U rows above, the factored rows, L below
+    //     (row pointers again: interchanges moved rows between positions)
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
-      const int row = cs + tid + NT * q;
-      if (row < n)
+      const int p = c0 + tid + NT * q;
+      if (p < n) {
+        T* wr = el.lrow(p) + cs;
 #pragma unroll
-        for (int j = 0; j < LWT; ++j)
-          if (j < lw) el.st(row, cs + j, x[q][j]);
+        for (int j = 0; j < SW; ++j)
+          if (j < sw) wr[j] = x[q][j];
+      }
     }
 #pragma unroll
-    for (int q = 0; q < QC; ++q) {
-      const int row = n + tid + NT * q;
-      if (row < N)
+    for (int q = 0; q < QC; ++q)
+      if (xrc[q])
 #pragma unroll
-        for (int j = 0; j < LWT; ++j)
-          if (j < lw) el.st(row, cs + j, xc[q][j]);
-    }
-    // leaf rows' own L (diagonal block, unit lower) into Lb[:, kp:kp+lw]
-    if (tid < lw) {
+        for (int j = 0; j < SW; ++j)
+          if (j < sw) xrc[q][j] = xc[q][j];
+    // the sub-panel rows' own unit-lower L (positions cs .. cs+sw-1 are
+    // slot 0 of threads kp .. kp+sw-1) into Lb[:, kp:kp+sw]
+    if (tid >= kp && tid < kp + sw) {
+      const int i = tid - kp;
 #pragma unroll
-      for (int j = 0; j < LWT; ++j) pb.Lb[tid * CT + kp + j] = (j < tid) ? x[0][j] : T(0);
+      for (int j = 0; j < SW; ++j) pb.Lb[i * CT + kp + j] = (j < i) ? x[0][j] : T(0);
     }
-    sync_global();
-    // leaf rows' L in the panel's earlier columns: Lb[:, 0:kp]
-    for (int q = tid; q < lw * kp; q += NT) {
-      const int i = q / kp, k = q % kp;
+    __syncthreads();
+    // their L in the panel's earlier columns: Lb[:, 0:kp] (written by earlier
+    // sub-panels, visible since the barrier at the top of this one)
+    for (int o = tid; o < sw * kp; o += NT) {
+      const int i = o / kp, k = o % kp;
       pb.Lb[i * CT + k] = el.ld(cs + i, c0 + k);
     }
     __syncthreads();
-    // (e) grow L_pp^{-1}: rows kp..kp+lw.  With L = [L11 0; L21 L22]:
+    // (6) grow L_pp^{-1} by rows kp .. kp+sw.  With L = [L11 0; L21 L22]:
     //     inv = [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}]
-    //     first  Y = L21 L11^{-1}  (lw x kp), then rows = -L22^{-1} Y and L22^{-1}
     {
-      T* Y = pb.Xu;  // reuse: lw x kp values, stored as Y[i * CT + k] (fits: LWT*CT <= CT*LWT)
-      for (int q = tid; q < lw * kp; q += NT) {
-        const int i = q / kp, k = q % kp;
-        T s = T(0);
-        for (int m = k; m < kp; ++m) s += pb.Lb[i * CT + m] * pb.Linv[m * LIS + k];
-        Y[i * CT + k] = s;
+      T* Y = pb.Xu;  // sw x kp values, Y[i * CT + k]
+      for (int o = tid; o < sw * kp; o += NT) {
+        const int i = o / kp, k = o % kp;
+        T acc = T(0);
+        for (int m = k; m < kp; ++m) acc += pb.Lb[i * CT + m] * pb.Linv[m * LIS + k];
+        Y[i * CT + k] = acc;
       }
       __syncthreads();
-      // L22^{-1} (unit lower lw x lw) by forward substitution, one thread per column
-      // then the new block row; done by threads (i, k) in sequence of i
-      if (tid < lw) {
+      if (tid < sw) {
         const int j = tid;
-        for (int i = 0; i < lw; ++i) {
-          T s = (i == j) ? T(1) : T(0);
+        for (int i = 0; i < sw; ++i) {
+          T acc = (i == j) ? T(1) : T(0);
           if (i > j)
-            for (int m = j; m < i; ++m) s -= pb.Lb[i * CT + kp + m] * pb.Linv[(kp + m) * LIS + kp + j];
-          pb.Linv[(kp + i) * LIS + kp + j] = s;
+            for (int m = j; m < i; ++m) acc -= pb.Lb[i * CT + kp + m] * pb.Linv[(kp + m) * LIS + kp + j];
+          pb.Linv[(kp + i) * LIS + kp + j] = acc;
         }
         for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * LIS + kp + j] = T(0);
       }
       __syncthreads();
-      for (int q = tid; q < lw * kp; q += NT) {
-        const int i = q / kp, k = q % kp;
-        T s = T(0);
-        for (int m = 0; m <= i; ++m) s += pb.Linv[(kp + i) * LIS + kp + m] * Y[m * CT + k];
-        pb.Linv[(kp + i) * LIS + k] = -s;
+      for (int o = tid; o < sw * kp; o += NT) {
+        const int i = o / kp, k = o % kp;
+        T acc = T(0);
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[(kp + i) * LIS + kp + m] * Y[m * CT + k];
+        pb.Linv[(kp + i) * LIS + k] = -acc;
       }
       __syncthreads();
     }
   }
+  sync_global();  // the panel's stores are read by the panel-row GEMM
 }
 
 // ---- the kernel -------------------------------------------------------------
 template <typename T>
 struct CondenseSmem {
   static constexpr int GEMM = 2 * (KC * (256 + 1 + 64 + 2));   // elements, both tile shapes
+  static constexpr int PANEL = CT * LIS + 2 * CT * SWMAX + SWMAX * CT + 2 * NW * SWMAX + 2 * SWMAX;
   static size_t bytes(int n) {
-    return sizeof(T) * (GEMM + CT * LIS + CT * LWMAX + LWMAX * CT + 4 * LWMAX + LWMAX * LWMAX) +
-           sizeof(PanelSmem) + 16 + sizeof(int) * n;
+    return sizeof(T) * (GEMM + PANEL) + sizeof(PanelSmem) + 16 + sizeof(int) * n;
   }
 };
 
 template <typename T, int QA, int QC, int LW>
-__device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
+__device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
   typedef Mfma<T> MF;
   const int tid = threadIdx.x;
   const int n = a.n, t = a.t, N = n + t;
@@ -580,10 +677,11 @@ __device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* sme
   PanelBufs<T> pb;
   pb.Linv = sg + CondenseSmem<T>::GEMM;
   pb.Xu = pb.Linv + CT * LIS;
-  pb.Lb = pb.Xu + CT * LWMAX;
-  pb.prow = pb.Lb + LWMAX * CT;
-  pb.krow = pb.prow + 2 * LWMAX;
-  pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * LWMAX + LWMAX * LWMAX);
+  pb.Ut = pb.Xu + CT * SWMAX;
+  pb.Lb = pb.Ut + CT * SWMAX;
+  pb.cand = pb.Lb + SWMAX * CT;
+  pb.krow = pb.cand + 2 * NW * SWMAX;
+  pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * SWMAX);
   int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
 
   Elem<T> el;
@@ -608,7 +706,7 @@ __device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* sme
     for (int r0 = c0; r0 < N; r0 += 256) {
       typename MF::acc_t acc[TA::RB][TA::CB];
       gemm_tile<T, 256, 64>(el, r0, N, c0, c1, c0, sg, acc);
-      for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) {
+      for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < N && col < c1) el.st(row, col, el.in(row, col) - v);
       });
     }
@@ -630,7 +728,7 @@ __device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* sme
       const int jl = min(j0 + 256, NC);
       typename MF::acc_t acc[TB::RB][TB::CB];
       gemm_tile<T, 64, 256>(el, c0, c1, j0, jl, c0, sg, acc);
-      map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) -> T {
+      map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
       });
       {
@@ -652,7 +750,7 @@ __device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* sme
           for (int cb = 0; cb < TB::CB; ++cb) acc[ib][cb] = nacc[cb];
         }
       }
-      for_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) {
+      for_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < c1 && col < jl) el.st(row, col, v);
       });
     }
@@ -664,7 +762,7 @@ __device__ void condense_one(const CondenseArgs<T>& a, int e, unsigned char* sme
       const int jl = min(j0 + 64, NC);
       typename MF::acc_t acc[TA::RB][TA::CB];
       gemm_tile<T, 256, 64>(el, r0, N, j0, jl, n, sg, acc);
-      for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) {
+      for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < N && col < jl) el.st(row, col, el.in(row, col) - v);
       });
     }
@@ -680,34 +778,35 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   condense_one<T, QA, QC, LW>(a, blockIdx.x, smem_raw);
 }
 
-// Persistent form over a work list of (segment, element) items whose
-// segments share (n, t): workgroup w takes items w, w + grid, ... in order.
+// Batched form over a work list of (segment, element) items whose segments
+// share (n, t): one workgroup per item, all items in one launch.  A
+// workgroup holds one CU's LDS and register budget, so the dispatcher hands
+// the next item to whichever CU finishes first (uneven elements balance).
 template <typename T, int QA, int QC, int LW>
-__global__ __launch_bounds__(NT) void condense_batched_kernel(const CondenseArgs<T>* segs, const int2* items,
-                                                              int n_items) {
+__global__ __launch_bounds__(NT) void condense_batched_kernel(const CondenseArgs<T>* segs, const int2* items) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-    const int2 w = items[it];
-    condense_one<T, QA, QC, LW>(segs[w.x], w.y, smem_raw);
-  }
+  const int2 w = items[blockIdx.x];
+  const CondenseArgs<T> a = segs[w.x];
+  condense_one<T, QA, QC, LW>(a, w.y, smem_raw);
 }
 
-// Leaf width chosen per local size n (set by the autotuner; default 4).
+// Sub-panel width chosen per (precision, local size n) by the autotuner;
+// 0 = not tuned.
 struct LeafChoice {
-  int n, lw;
+  int prec, n, lw;
 };
-static LeafChoice g_leaf_choice[16];
+static LeafChoice g_leaf_choice[32];
 static int g_leaf_choices = 0;
 
-static int leaf_width_for(int n) {
+static int leaf_width_for(int prec, int n) {
   for (int i = 0; i < g_leaf_choices; ++i)
-    if (g_leaf_choice[i].n == n) return g_leaf_choice[i].lw;
-  return 4;
+    if (g_leaf_choice[i].prec == prec && g_leaf_choice[i].n == n) return g_leaf_choice[i].lw;
+  return 0;
 }
 
 template <typename T, int QA, int QC, int LW>
 static hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
-                                     int n_items, int grid, hipStream_t s) {
+                                     int n_items, hipStream_t s) {
   const size_t smem = CondenseSmem<T>::bytes(a.n);
   if (!segs) {
     auto kern = condense_kernel<T, QA, QC, LW>;
@@ -720,34 +819,32 @@ static hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArg
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    // grid = resident workgroups per CU x CUs (argument `grid` is the CU count)
-    int per_cu = 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, smem) !=
-            hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    grid = std::min(n_items, per_cu * grid);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), smem, s, segs, items, n_items);
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(NT), smem, s, segs, items);
   }
   return hipGetLastError();
 }
 
 template <typename T, int QA, int QC>
 static hipError_t launch_condense(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
-                                  int n_items, int grid, hipStream_t s) {
-  if constexpr (QA <= 3) {
-    if (leaf_width_for(a.n) == 8) return launch_condense_lw<T, QA, QC, 8>(a, segs, items, n_items, grid, s);
-  }
-  return launch_condense_lw<T, QA, QC, 4>(a, segs, items, n_items, grid, s);
+                                  int n_items, hipStream_t s) {
+  // 16-wide sub-panels keep (QA + QC) x 16 values in registers.  Untuned
+  // default: 16 where that stays within the register file without spilling
+  // (FP32 up to 4 rows per thread, FP64 up to 2), else 8.
+  constexpr bool fp64 = sizeof(T) == 8;
+  constexpr int def = (fp64 ? QA + QC <= 2 : QA + QC <= 4) ? 16 : 8;
+  int lw = leaf_width_for(fp64 ? IEDG_F64 : IEDG_F32, a.n);
+  if (lw == 0) lw = def;
+  if (lw == 16) return launch_condense_lw<T, QA, QC, 16>(a, segs, items, n_items, s);
+  return launch_condense_lw<T, QA, QC, 8>(a, segs, items, n_items, s);
 }
 
 template <typename T>
 static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, const CondenseArgs<T>* segs = nullptr,
-                                    const int2* items = nullptr, int n_items = 0, int grid = 0) {
+                                    const int2* items = nullptr, int n_items = 0) {
   const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
-  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, segs, items, n_items, grid, s);
-  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, segs, items, n_items, grid, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, segs, items, n_items, grid, s);
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, segs, items, n_items, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, segs, items, n_items, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, segs, items, n_items, s);
   return hipErrorInvalidValue;
 }
 
@@ -867,7 +964,7 @@ extern "C" iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32
 // ---- batched condensation ---------------------------------------------------
 struct iedg_batch_s {
   iedg_context ctx = nullptr;
-  int n = 0, t = 0, n_items = 0, grid = 0;
+  int n = 0, t = 0, n_items = 0;
   iedg_prec prec = IEDG_F64;
   void* d_segs = nullptr;   // CondenseArgs<T>[n_seg]
   int2* d_items = nullptr;  // (segment, element) work list
@@ -911,9 +1008,6 @@ extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const 
   b->t = n_trace_elem;
   b->prec = prec;
   b->n_items = (int)items.size();
-  int dev = 0, ncu = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = ncu;  // scaled by the kernel's occupancy at launch
   const size_t seg_bytes = prec == IEDG_F64 ? a64.size() * sizeof(a64[0]) : a32.size() * sizeof(a32[0]);
   hipError_t e = hipMalloc(&b->d_segs, seg_bytes);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_items), std::max<size_t>(1, items.size()) * sizeof(int2));
@@ -938,10 +1032,10 @@ extern "C" iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch b, hip
   hipError_t err;
   if (b->prec == IEDG_F64)
     err = dispatch_condense<double>(b->proto64, stream, (const CondenseArgs<double>*)b->d_segs, b->d_items,
-                                    b->n_items, b->grid);
+                                    b->n_items);
   else
     err = dispatch_condense<float>(b->proto32, stream, (const CondenseArgs<float>*)b->d_segs, b->d_items,
-                                   b->n_items, b->grid);
+                                   b->n_items);
   if (err != hipSuccess) return hip_check(ctx, err, "condense_batched launch");
   return IEDG_OK;
 }
@@ -953,15 +1047,15 @@ extern "C" void iedg_batch_destroy(iedg_batch b) {
   delete b;
 }
 
-extern "C" iedg_status iedg_set_leaf_width(iedg_context ctx, int32_t n_local, int32_t leaf_width) {
-  if (!ctx || n_local <= 0 || (leaf_width != 4 && leaf_width != 8))
-    return set_error(ctx, IEDG_ERR_INVALID_ARG, "set_leaf_width: leaf width must be 4 or 8");
+extern "C" iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int32_t n_local, int32_t leaf_width) {
+  if (!ctx || n_local <= 0 || (prec != IEDG_F64 && prec != IEDG_F32) || (leaf_width != 8 && leaf_width != 16))
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "set_leaf_width: precision F64/F32, sub-panel width 8 or 16");
   for (int i = 0; i < g_leaf_choices; ++i)
-    if (g_leaf_choice[i].n == n_local) {
+    if (g_leaf_choice[i].prec == (int)prec && g_leaf_choice[i].n == n_local) {
       g_leaf_choice[i].lw = leaf_width;
       return IEDG_OK;
     }
-  if (g_leaf_choices >= 16) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "set_leaf_width: table full");
-  g_leaf_choice[g_leaf_choices++] = LeafChoice{n_local, leaf_width};
+  if (g_leaf_choices >= 32) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "set_leaf_width: table full");
+  g_leaf_choice[g_leaf_choices++] = LeafChoice{(int)prec, n_local, leaf_width};
   return IEDG_OK;
 }

@@ -164,7 +164,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--forms", default="mixed,bf16,fp64",
+                    help="mixed: FP32 condensation; bf16: BF16-operand condensation; fp64: plain FP64")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dims", default="16,16,8")
@@ -201,7 +202,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_1605_01020_amd import api, F64, F32
+    from paper_1605_01020_amd import api, F64, F32, BF16
     from paper_1605_01020_amd.solver import NewtonStepSolver, StepTimer
     import synth.device as sd
     from synth import StructuredHexMesh, ElementSpec
@@ -214,6 +215,8 @@ def main():
     E, n, t = hmesh.n_elem, spec.n, spec.t
     torch.cuda.set_device(0)
     ctx = api.Context(0)
+    from paper_1605_01020_amd.autotune import apply_tuning
+    apply_tuning(ctx)
     mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b)
     print(f"[bench] {dims} p={args.p}: E={E} n={n} t={t} faces={hmesh.n_face} nnzb={mesh.nnzb}", file=sys.stderr,
           flush=True)
@@ -236,7 +239,8 @@ def main():
             if form == "fp64":
                 z, u, info = solver.solve_fp64(A, B, C, D, F, G, rtol=args.tol, timer=timer)
             else:
-                z, u, info = solver.solve_mixed(A, B, C, D, F, G, tol=args.tol, prec=F32, timer=timer)
+                z, u, info = solver.solve_mixed(A, B, C, D, F, G, tol=args.tol, prec=BF16 if form == "bf16" else F32,
+                                                timer=timer)
             if record:
                 cond_ms.append(info["phases_ms"].get("condense", float("nan")))
                 iters.append(info["iters"])
@@ -303,6 +307,8 @@ def main():
     }
     if "fp64" in results and "mixed" in results:
         out["speedup_mixed_vs_fp64"] = results["mixed"]["solves_per_s"] / results["fp64"]["solves_per_s"]
+    if "fp64" in results and "bf16" in results:
+        out["speedup_bf16_vs_fp64"] = results["bf16"]["solves_per_s"] / results["fp64"]["solves_per_s"]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl.seed, wl.restart)

@@ -63,7 +63,7 @@ class Simulation:
     buffers of the solve and of its refinement."""
 
     def __init__(self, ctx, case, seed, prec=F32, restart=100, n_refine=1, tol=1e-8, inner_rtol=1e-6,
-                 correction_rtol=1e-3, ordering="colour"):
+                 correction_rtol=1e-3, ordering="colour", cycle_steps=40):
         from synth.mesh import StructuredHexMesh
         self.ctx, self.case, self.seed, self.prec = ctx, case, seed, prec
         self.tol, self.inner_rtol, self.correction_rtol = tol, inner_rtol, correction_rtol
@@ -96,7 +96,10 @@ class Simulation:
         self.dz = torch.empty((E, n), **f64)
         # one residual-sum slot per refinement residual (stage 0 .. n_refine)
         self.sums = torch.zeros((n_refine + 1, 4), **f64)
-        self.gm = [api.GmresState(ctx, self.mesh, restart) for _ in range(n_refine + 1)]
+        # device-driven cycles stop at cycle_steps Arnoldi steps (every step
+        # is enqueued, later ones return at once after convergence); a cycle
+        # that stops unconverged is continued by the refinement on the host
+        self.gm = [api.GmresState(ctx, self.mesh, min(restart, cycle_steps)) for _ in range(n_refine + 1)]
         self.restart = restart
 
     @staticmethod

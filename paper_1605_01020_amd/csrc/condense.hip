@@ -210,25 +210,61 @@ struct SlabLoader {
   }
 };
 
-template <typename T, int TM, int TN>
+// Round to nearest even FP32 -> BF16 (bit pattern); NaN stays NaN.
+__device__ __attribute__((always_inline)) inline short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// MM = 0: MFMA in T.  MM = 1 (T = float): operands rounded to BF16, FP32
+// accumulation, v_mfma_f32_16x16x16_bf16 (A operand: lane l holds
+// A[l % 16][4 (l / 16) + i], B operand: B[4 (l / 16) + i][l % 16], i < 4;
+// accumulator as for the FP32 16x16x4 operation).
+template <typename T, int TM, int TN, int MM>
 __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, int wr0, int wc0,
                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
   typedef Tile<T, TM, TN> TL;
   typedef Mfma<T> MF;
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
-  const T* As = stage + wr0 + li + lg * TL::SA;
-  const T* Bs = stage + KC * TL::SA + wc0 + li + lg * TL::SB;
+  if constexpr (MM == 0) {
+    const T* As = stage + wr0 + li + lg * TL::SA;
+    const T* Bs = stage + KC * TL::SA + wc0 + li + lg * TL::SB;
 #pragma unroll
-  for (int ks = 0; ks < KC / 4; ++ks) {
-    T av[TL::RB], bv[TL::CB];
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      T av[TL::RB], bv[TL::CB];
 #pragma unroll
-    for (int rb = 0; rb < TL::RB; ++rb) av[rb] = As[4 * ks * TL::SA + 16 * rb];
+      for (int rb = 0; rb < TL::RB; ++rb) av[rb] = As[4 * ks * TL::SA + 16 * rb];
 #pragma unroll
-    for (int cb = 0; cb < TL::CB; ++cb) bv[cb] = Bs[4 * ks * TL::SB + 16 * cb];
+      for (int cb = 0; cb < TL::CB; ++cb) bv[cb] = Bs[4 * ks * TL::SB + 16 * cb];
 #pragma unroll
-    for (int rb = 0; rb < TL::RB; ++rb)
+      for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
+        for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::mac(av[rb], bv[cb], acc[rb][cb]);
+    }
+  } else {
+    static_assert(sizeof(T) == 4 && KC % 16 == 0, "BF16 operands need FP32 slabs");
+    const T* As = stage + wr0 + li + 4 * lg * TL::SA;
+    const T* Bs = stage + KC * TL::SA + wc0 + li + 4 * lg * TL::SB;
+#pragma unroll
+    for (int ks = 0; ks < KC / 16; ++ks) {
+      bf16x4 av[TL::RB], bv[TL::CB];
+#pragma unroll
+      for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[rb][i] = to_bf16(As[(16 * ks + i) * TL::SA + 16 * rb]);
+#pragma unroll
+      for (int cb = 0; cb < TL::CB; ++cb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[cb][i] = to_bf16(Bs[(16 * ks + i) * TL::SB + 16 * cb]);
+#pragma unroll
+      for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < TL::CB; ++cb)
+          acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[rb], bv[cb], acc[rb][cb], 0, 0, 0);
+    }
   }
 }
 
@@ -239,7 +275,7 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
 // the global loads of the next two slabs in flight in two register buffers.
 // The slab loop is unrolled by two so that stage and buffer indices are
 // compile-time constants.
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, int MM = 0>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
   typedef Tile<T, TM, TN> TL;
@@ -268,14 +304,14 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
       ld.store(S1, a1, b1);
       if (ch + 3 < nch) ld.load(ch + 3, a1, b1);
     }
-    slab_mma<T, TM, TN>(S0, wr0, wc0, acc);
+    slab_mma<T, TM, TN, MM>(S0, wr0, wc0, acc);
     __syncthreads();
     if (ch + 1 < nch) {
       if (ch + 2 < nch) {
         ld.store(S0, a0, b0);
         if (ch + 4 < nch) ld.load(ch + 4, a0, b0);
       }
-      slab_mma<T, TM, TN>(S1, wr0, wc0, acc);
+      slab_mma<T, TM, TN, MM>(S1, wr0, wc0, acc);
       __syncthreads();
     }
   }
@@ -668,7 +704,7 @@ struct CondenseSmem {
   }
 };
 
-template <typename T, int QA, int QC, int LW>
+template <typename T, int QA, int QC, int LW, int MM>
 __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
   typedef Mfma<T> MF;
   const int tid = threadIdx.x;
@@ -705,7 +741,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     // 1. panel column in Crout order
     for (int r0 = c0; r0 < N; r0 += 256) {
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, 256, 64>(el, r0, N, c0, c1, c0, sg, acc);
+      gemm_tile<T, 256, 64, MM>(el, r0, N, c0, c1, c0, sg, acc);
       for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < N && col < c1) el.st(row, col, el.in(row, col) - v);
       });
@@ -727,7 +763,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = c1; j0 < NC; j0 += 256) {
       const int jl = min(j0 + 256, NC);
       typename MF::acc_t acc[TB::RB][TB::CB];
-      gemm_tile<T, 64, 256>(el, c0, c1, j0, jl, c0, sg, acc);
+      gemm_tile<T, 64, 256, MM>(el, c0, c1, j0, jl, c0, sg, acc);
       map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
       });
@@ -761,7 +797,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = n; j0 < NC; j0 += 64) {
       const int jl = min(j0 + 64, NC);
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, 256, 64>(el, r0, N, j0, jl, n, sg, acc);
+      gemm_tile<T, 256, 64, MM>(el, r0, N, j0, jl, n, sg, acc);
       for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < N && col < jl) el.st(row, col, el.in(row, col) - v);
       });
@@ -772,22 +808,22 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
 }
 
 // One element per workgroup.
-template <typename T, int QA, int QC, int LW>
+template <typename T, int QA, int QC, int LW, int MM>
 __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  condense_one<T, QA, QC, LW>(a, blockIdx.x, smem_raw);
+  condense_one<T, QA, QC, LW, MM>(a, blockIdx.x, smem_raw);
 }
 
 // Batched form over a work list of (segment, element) items whose segments
 // share (n, t): one workgroup per item, all items in one launch.  A
 // workgroup holds one CU's LDS and register budget, so the dispatcher hands
 // the next item to whichever CU finishes first (uneven elements balance).
-template <typename T, int QA, int QC, int LW>
+template <typename T, int QA, int QC, int LW, int MM>
 __global__ __launch_bounds__(NT) void condense_batched_kernel(const CondenseArgs<T>* segs, const int2* items) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 w = items[blockIdx.x];
   const CondenseArgs<T> a = segs[w.x];
-  condense_one<T, QA, QC, LW>(a, w.y, smem_raw);
+  condense_one<T, QA, QC, LW, MM>(a, w.y, smem_raw);
 }
 
 // Sub-panel width chosen per (precision, local size n) by the autotuner;
@@ -804,18 +840,18 @@ static int leaf_width_for(int prec, int n) {
   return 0;
 }
 
-template <typename T, int QA, int QC, int LW>
+template <typename T, int QA, int QC, int LW, int MM>
 static hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
                                      int n_items, hipStream_t s) {
   const size_t smem = CondenseSmem<T>::bytes(a.n);
   if (!segs) {
-    auto kern = condense_kernel<T, QA, QC, LW>;
+    auto kern = condense_kernel<T, QA, QC, LW, MM>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
   } else {
-    auto kern = condense_batched_kernel<T, QA, QC, LW>;
+    auto kern = condense_batched_kernel<T, QA, QC, LW, MM>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
@@ -824,7 +860,7 @@ static hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArg
   return hipGetLastError();
 }
 
-template <typename T, int QA, int QC>
+template <typename T, int QA, int QC, int MM>
 static hipError_t launch_condense(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
                                   int n_items, hipStream_t s) {
   // 16-wide sub-panels keep (QA + QC) x 16 values in registers.  Untuned
@@ -834,17 +870,17 @@ static hipError_t launch_condense(const CondenseArgs<T>& a, const CondenseArgs<T
   constexpr int def = (fp64 ? QA + QC <= 2 : QA + QC <= 4) ? 16 : 8;
   int lw = leaf_width_for(fp64 ? IEDG_F64 : IEDG_F32, a.n);
   if (lw == 0) lw = def;
-  if (lw == 16) return launch_condense_lw<T, QA, QC, 16>(a, segs, items, n_items, s);
-  return launch_condense_lw<T, QA, QC, 8>(a, segs, items, n_items, s);
+  if (lw == 16) return launch_condense_lw<T, QA, QC, 16, MM>(a, segs, items, n_items, s);
+  return launch_condense_lw<T, QA, QC, 8, MM>(a, segs, items, n_items, s);
 }
 
-template <typename T>
+template <typename T, int MM = 0>
 static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, const CondenseArgs<T>* segs = nullptr,
                                     const int2* items = nullptr, int n_items = 0) {
   const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
-  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1>(a, segs, items, n_items, s);
-  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1>(a, segs, items, n_items, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2>(a, segs, items, n_items, s);
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1, MM>(a, segs, items, n_items, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1, MM>(a, segs, items, n_items, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, MM>(a, segs, items, n_items, s);
   return hipErrorInvalidValue;
 }
 
@@ -924,10 +960,10 @@ extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n
     CondenseArgs<double> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
                            (double*)LU, (double*)U12, (double*)L21, (double*)Ke, perm, w, r, ctx->d_status};
     err = dispatch_condense<double>(a, stream);
-  } else if (prec == IEDG_F32) {
+  } else if (prec == IEDG_F32 || prec == IEDG_BF16) {
     CondenseArgs<float> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
                           (float*)LU, (float*)U12, (float*)L21, (float*)Ke, perm, w, r, ctx->d_status};
-    err = dispatch_condense<float>(a, stream);
+    err = prec == IEDG_F32 ? dispatch_condense<float, 0>(a, stream) : dispatch_condense<float, 1>(a, stream);
   } else {
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: precision %d not built", (int)prec);
   }
@@ -978,7 +1014,8 @@ extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const 
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: bad arguments");
   if ((n_local & 3) || (n_trace_elem & 1) || n_local > 5 * NT || n_trace_elem > 2 * NT)
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: n=%d t=%d", n_local, n_trace_elem);
-  if (prec != IEDG_F64 && prec != IEDG_F32) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: precision");
+  if (prec != IEDG_F64 && prec != IEDG_F32 && prec != IEDG_BF16)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: precision");
   *out = nullptr;
   std::vector<int2> items;
   std::vector<CondenseArgs<double>> a64;
@@ -1033,6 +1070,9 @@ extern "C" iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch b, hip
   if (b->prec == IEDG_F64)
     err = dispatch_condense<double>(b->proto64, stream, (const CondenseArgs<double>*)b->d_segs, b->d_items,
                                     b->n_items);
+  else if (b->prec == IEDG_BF16)
+    err = dispatch_condense<float, 1>(b->proto32, stream, (const CondenseArgs<float>*)b->d_segs, b->d_items,
+                                      b->n_items);
   else
     err = dispatch_condense<float>(b->proto32, stream, (const CondenseArgs<float>*)b->d_segs, b->d_items,
                                    b->n_items);

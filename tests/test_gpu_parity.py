@@ -311,3 +311,60 @@ def test_condense_parity_fp32(ctx, dims, p):
         assert np.isfinite(ke).all() and np.isfinite(rr).all()
         assert rel(ke, Ke) <= 2e-5, (e, rel(ke, Ke))
         assert rel(rr, re) <= 2e-5, (e, rel(rr, re))
+
+
+@pytest.mark.parametrize("dims,p", CASES)
+def test_condense_parity_bf16(ctx, dims, p):
+    """BF16 operands in the condensation's trailing updates (FP32
+    accumulation, FP32 panels).  Each operand rounding is at most 2^-9
+    relative, so a product term carries at most 2^-8; the bound allows a
+    factor 4 of growth through A^{-1} (its spectrum lies in a disk of radius
+    about 1 around 2): the correction term C A^{-1} B of K_e is within
+    2^-6 of itself, hence |K_e - K| <= 2^-6 |C A^{-1} B| (+ FP32 rounding),
+    and r_e = -C A^{-1} F within 2^-6 relative."""
+    from paper_1605_01020_amd import BF16
+    m, spec, blocks, G = host_case(dims, p)
+    _say(f"condense bf16 {dims} p={p}")
+    d = host_blocks_to_dev(blocks)
+    fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=BF16)
+    ctx.sync_status()
+    worst_k = worst_r = 0.0
+    for e, blk in enumerate(blocks):
+        Ke, re, _ = oracle.condense_element(blk["A"], blk["B"], blk["C"], blk["D"], blk["F"])
+        corr = np.linalg.norm(blk["D"] - Ke)
+        ke = fac["Ke"][e].double().cpu().numpy()
+        rr = fac["r"][e].cpu().numpy()
+        assert np.isfinite(ke).all() and np.isfinite(rr).all()
+        err_k = np.linalg.norm(ke - Ke)
+        assert err_k <= 2.0 ** -6 * corr + 2e-5 * np.linalg.norm(Ke), (e, err_k, corr)
+        assert rel(rr, re) <= 2.0 ** -6, (e, rel(rr, re))
+        worst_k = max(worst_k, err_k / corr)
+        worst_r = max(worst_r, rel(rr, re))
+    _say(f"bf16 worst |dK|/|CA^-1B| = {worst_k:.2e}, worst rel r = {worst_r:.2e}")
+    # the factors still satisfy P A = L U to FP32-and-BF16 accuracy
+    LU = fac["LU"].double().cpu().numpy()
+    perm = fac["perm"].cpu().numpy()
+    for e in (0, len(blocks) - 1):
+        F_ = LU[e][perm[e]]
+        L = np.tril(F_, -1) + np.eye(F_.shape[0])
+        U = np.triu(F_)
+        A = blocks[e]["A"][perm[e]]
+        assert np.linalg.norm(L @ U - A) <= 2.0 ** -6 * np.linalg.norm(A)
+
+
+def test_config0_mixed_bf16_refinement(ctx, cfg0_oracle):
+    import synth.device as sd
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    from paper_1605_01020_amd import BF16
+    wl, m, spec, tm, blocks, G, ref = cfg0_oracle
+    mesh = _mesh(ctx, m, spec)
+    _say("config 0 mixed bf16 + refinement")
+    d = sd.gen_blocks(spec, wl.seed, 0, m.n_elem, which="ABCDF")
+    Gd = sd.gen_trace_rhs(spec, wl.seed, 0, m.n_face)
+    s = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
+    z, uhat, info = s.solve_mixed(d["A"], d["B"], d["C"], d["D"], d["F"], Gd, tol=1e-8, prec=BF16)
+    ctx.sync_status()
+    _say(f"bf16 refinement history {info['rho_hist']}")
+    assert info["converged_full"], info
+    assert rel(uhat.cpu().numpy(), ref["uhat"]) <= 1e-7
+    assert rel(z.cpu().numpy(), np.stack(ref["z"])) <= 1e-7

@@ -134,15 +134,22 @@ struct Tile {
 };
 
 // Per-thread global-load descriptors of one k-slab (compile-time counts).
-template <typename T, int TM, int TN>
+// Every load is issued unconditionally (out-of-range lanes read a valid
+// address and discard the value), so the compiler can count the loads in
+// flight and the wait before storing a slab covers only that slab's loads:
+// the next slab's loads stay in flight behind the MFMA work.  HASW: the
+// tile includes the right-hand-side column (w, FP64 storage).
+template <typename T, int TM, int TN, bool HASW>
 struct SlabLoader {
   typedef Tile<T, TM, TN> TL;
   typedef typename Pair<T>::v P2;
   const T* aptr[TL::AL];
   int ak[TL::AL], arow[TL::AL];
+  bool aok[TL::AL];
   const T* bbase[TL::BL];
   const double* bw[TL::BL];
   int bstride[TL::BL], bk[TL::BL], bcol[TL::BL], bn[TL::BL];
+  bool isw[TL::BL];
   const int* sperm;
   int K;
 
@@ -156,7 +163,8 @@ struct SlabLoader {
       arow[q] = idx / (KC / 2);
       ak[q] = 2 * (idx % (KC / 2));
       const int row = r0 + arow[q];
-      aptr[q] = row < rlim ? el.lrow(row) : nullptr;
+      aok[q] = row < rlim;
+      aptr[q] = aok[q] ? el.lrow(row) : el.LU;
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) {
@@ -165,48 +173,56 @@ struct SlabLoader {
       bcol[q] = 2 * (idx % (TN / 2));
       const int col = c0 + bcol[q];
       bn[q] = col >= clim ? 0 : (col + 1 >= clim ? 1 : 2);
-      bw[q] = nullptr;
+      isw[q] = false;
+      bw[q] = el.A;  // a valid address when unused
       bbase[q] = el.LU;
       bstride[q] = 0;
       if (col < el.n) { bbase[q] = el.LU + col; bstride[q] = el.n; }
       else if (col < el.N) { bbase[q] = el.U12 + (col - el.n); bstride[q] = el.t; }
-      else { bw[q] = el.w; }
+      else if (HASW && col < clim) { isw[q] = true; bw[q] = el.w; }
     }
   }
-  __device__ __attribute__((always_inline)) inline void load(int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL]) const {
+  // raw loads only: the values are masked when the slab is stored, two
+  // slabs later, so nothing waits for them here
+  __device__ __attribute__((always_inline)) inline void load(int ch, P2 (&va)[TL::AL], P2 (&vb)[TL::BL],
+                                                             double (&vw)[HASW ? TL::BL : 1]) const {
     const int k0 = ch * KC;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
       const int k = k0 + ak[q];
-      P2 v;
-      v.x = T(0); v.y = T(0);
-      if (aptr[q] && k < K) v = *reinterpret_cast<const P2*>(aptr[q] + k);
-      va[q] = v;
+      va[q] = *reinterpret_cast<const P2*>(aptr[q] + (k < K ? k : 0));
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) {
       const int k = k0 + bk[q];
-      P2 v;
-      v.x = T(0); v.y = T(0);
-      if (k < K && bn[q]) {
-        const size_t pr = (size_t)sperm[k];
-        if (bw[q]) v.x = (T)bw[q][pr];
-        else if (bn[q] == 2) v = *reinterpret_cast<const P2*>(bbase[q] + pr * bstride[q]);
-        else v.x = bbase[q][pr * bstride[q]];
-      }
-      vb[q] = v;
+      const size_t pr = (size_t)sperm[k < K ? k : 0];
+      vb[q] = *reinterpret_cast<const P2*>(bbase[q] + pr * bstride[q]);
+      if constexpr (HASW) vw[q] = bw[q][isw[q] ? pr : 0];
     }
   }
-  __device__ __attribute__((always_inline)) inline void store(T* stage, const P2 (&va)[TL::AL], const P2 (&vb)[TL::BL]) const {
+  __device__ __attribute__((always_inline)) inline void store(int ch, T* stage, const P2 (&va)[TL::AL],
+                                                              const P2 (&vb)[TL::BL],
+                                                              const double (&vw)[HASW ? TL::BL : 1]) const {
+    const int k0 = ch * KC;
     T* As = stage;
     T* Bs = stage + KC * TL::SA;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
-      As[ak[q] * TL::SA + arow[q]] = va[q].x;
-      As[(ak[q] + 1) * TL::SA + arow[q]] = va[q].y;
+      const bool ok = aok[q] && k0 + ak[q] < K;
+      As[ak[q] * TL::SA + arow[q]] = ok ? va[q].x : T(0);
+      As[(ak[q] + 1) * TL::SA + arow[q]] = ok ? va[q].y : T(0);
     }
 #pragma unroll
-    for (int q = 0; q < TL::BL; ++q) *reinterpret_cast<P2*>(Bs + bk[q] * TL::SB + bcol[q]) = vb[q];
+    for (int q = 0; q < TL::BL; ++q) {
+      const bool ok = k0 + bk[q] < K;
+      P2 r;
+      r.x = (ok && bn[q] >= 1) ? vb[q].x : T(0);
+      r.y = (ok && bn[q] == 2) ? vb[q].y : T(0);
+      if constexpr (HASW) {
+        if (isw[q]) r.x = ok ? (T)vw[q] : T(0);
+      }
+      *reinterpret_cast<P2*>(Bs + bk[q] * TL::SB + bcol[q]) = r;
+    }
   }
 };
 
@@ -275,7 +291,7 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
 // the global loads of the next two slabs in flight in two register buffers.
 // The slab loop is unrolled by two so that stage and buffer indices are
 // compile-time constants.
-template <typename T, int TM, int TN, int MM = 0>
+template <typename T, int TM, int TN, int MM = 0, bool HASW = false>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
   typedef Tile<T, TM, TN> TL;
@@ -289,28 +305,28 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
     for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::zero();
   if (K <= 0) return;
   const int nch = (K + KC - 1) / KC;
-  SlabLoader<T, TM, TN> ld;
+  SlabLoader<T, TM, TN, HASW> ld;
   ld.init(el, r0, rlim, c0, clim, K);
   T* S0 = smem;
   T* S1 = smem + TL::STAGE;
   P2 a0[TL::AL], b0[TL::BL], a1[TL::AL], b1[TL::BL];
-  ld.load(0, a0, b0);
-  if (nch > 1) ld.load(1, a1, b1);
-  ld.store(S0, a0, b0);
-  if (nch > 2) ld.load(2, a0, b0);
+  double w0[HASW ? TL::BL : 1], w1[HASW ? TL::BL : 1];
+  // loads past the last slab are issued too (they read valid addresses and
+  // are masked): the same loads are in flight on every path, so each wait
+  // before a store covers exactly the slab being stored
+  ld.load(0, a0, b0, w0);
+  ld.load(1, a1, b1, w1);
+  ld.store(0, S0, a0, b0, w0);
+  ld.load(2, a0, b0, w0);
   __syncthreads();
   for (int ch = 0; ch < nch; ch += 2) {
-    if (ch + 1 < nch) {
-      ld.store(S1, a1, b1);
-      if (ch + 3 < nch) ld.load(ch + 3, a1, b1);
-    }
+    ld.store(ch + 1, S1, a1, b1, w1);
+    ld.load(ch + 3, a1, b1, w1);
     slab_mma<T, TM, TN, MM>(S0, wr0, wc0, acc);
     __syncthreads();
     if (ch + 1 < nch) {
-      if (ch + 2 < nch) {
-        ld.store(S0, a0, b0);
-        if (ch + 4 < nch) ld.load(ch + 4, a0, b0);
-      }
+      ld.store(ch + 2, S0, a0, b0, w0);
+      ld.load(ch + 4, a0, b0, w0);
       slab_mma<T, TM, TN, MM>(S1, wr0, wc0, acc);
       __syncthreads();
     }
@@ -763,7 +779,10 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = c1; j0 < NC; j0 += 256) {
       const int jl = min(j0 + 256, NC);
       typename MF::acc_t acc[TB::RB][TB::CB];
-      gemm_tile<T, 64, 256, MM>(el, c0, c1, j0, jl, c0, sg, acc);
+      if (jl > N)  // this tile holds the right-hand-side column
+        gemm_tile<T, 64, 256, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
+      else
+        gemm_tile<T, 64, 256, MM, false>(el, c0, c1, j0, jl, c0, sg, acc);
       map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
       });
@@ -797,7 +816,10 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = n; j0 < NC; j0 += 64) {
       const int jl = min(j0 + 64, NC);
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, 256, 64, MM>(el, r0, N, j0, jl, n, sg, acc);
+      if (jl > N)
+        gemm_tile<T, 256, 64, MM, true>(el, r0, N, j0, jl, n, sg, acc);
+      else
+        gemm_tile<T, 256, 64, MM, false>(el, r0, N, j0, jl, n, sg, acc);
       for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
         if (row < N && col < jl) el.st(row, col, el.in(row, col) - v);
       });

@@ -84,6 +84,30 @@ def cpu_baseline(seed, restart):
             "condense_elems_per_s": sub.n_elem / med[0]}
 
 
+def measured_traffic(kernel_sources, profile):
+    """HBM bytes per launch from a rocprofv3 counter summary, or None when the
+    kernel source (or its tuning table) changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for src in kernel_sources:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source-sha256 (condense.hip + tuning.json)") != h.hexdigest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -282,6 +306,10 @@ def main():
     flops = condense_flops(n, t) * E
     peak = FP32_PEAK_TFLOPS if head == "mixed" else FP64_PEAK_TFLOPS
     achieved = flops / (r["condense_ms"] * 1e-3) / 1e12
+    traffic = None
+    if head == "mixed" and dims == (16, 16, 8) and args.p == 3:
+        traffic = measured_traffic(["paper_1605_01020_amd/csrc/condense.hip", "paper_1605_01020_amd/tuning.json"],
+                                   "condense_f32_16x16x8_p3_hbm_traffic.md")
     out = {
         "metric": "Newton-step solves/s at relative residual 1e-8 (mixed FP32/FP64 form; FP64 form beside it)",
         "value": r["solves_per_s"],
@@ -302,7 +330,7 @@ def main():
         "lat_ms": r["lat_ms"],
         "forms": results,
         "roofline": {"bound": "mfma", "kernel": "condense", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops},
     }
     if "fp64" in results and "mixed" in results:

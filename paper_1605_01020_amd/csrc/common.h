@@ -95,6 +95,39 @@ __device__ inline double wave_dot(const T* row, const double* vec, int len) {
   return wave_sum(s);
 }
 
+// Dot products of R contiguous rows (len values each) with one LDS vector by
+// one wave: 4 loads per row in flight per lane, all rows' loads issued
+// together.  rows[r] must be a valid address even when unused (its result
+// is ignored).  Every lane receives every sum.
+template <typename T, int R>
+__device__ inline void wave_dot_rows(const T* const (&rows)[R], const double* vec, int len, double (&out)[R]) {
+  const int lane = threadIdx.x & 63;
+  double s[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) s[r] = 0.0;
+  for (int k0 = lane; k0 < len; k0 += 64 * 4) {
+    T v[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 64 * j;
+        v[r][j] = rows[r][k < len ? k : 0];
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 64 * j;
+      if (k < len) {
+        const double x = vec[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] += (double)v[r][j] * x;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = wave_sum(s[r]);
+}
+
 // Device status word: first failing index (element or block row) + code.
 struct DeviceStatus {
   int32_t code;   // 0 = ok, otherwise an iedg_status value

@@ -907,7 +907,10 @@ static hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, con
 }
 
 // ---- right-hand side condensation: w = L^{-1} P F, r = -L21 w ----------
-// Position i of P A is physical row perm[i] of LU and of w.
+// Position i of P A is physical row perm[i] of LU and of w.  Rows are taken
+// four per wave at a time (wave_dot_rows, 16 loads in flight per lane);
+// 64-row diagonal blocks of L are staged in LDS in the storage precision and
+// solved by one wave.  LDS stays small so that several elements share a CU.
 constexpr int RTHR = 256;
 
 template <typename T>
@@ -915,10 +918,11 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
                                                             const T* L21, const double* F, double* w,
                                                             double* r) {
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int RW = RTHR / 64;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* y = reinterpret_cast<double*>(smem_raw);  // n
-  double* blk = y + n;                              // 64 x 65
-  int* sp = reinterpret_cast<int*>(blk + 64 * 65);  // n
+  double* y = reinterpret_cast<double*>(smem_raw);      // n
+  int* sp = reinterpret_cast<int*>(y + n);              // n
+  T* blk = reinterpret_cast<T*>(sp + ((n + 3) & ~3));  // 64 x 65
   const T* L = LU + (size_t)e * n * n;
   const int32_t* p = perm + (size_t)e * n;
   const double* f = F + (size_t)e * n;
@@ -929,20 +933,31 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   __syncthreads();
   for (int i0 = 0; i0 < n; i0 += 64) {
     const int i1 = min(i0 + 64, n), bw = i1 - i0;
-    for (int i = i0 + wv; i < i1; i += RTHR / 64) {
-      const double s = wave_dot<T>(L + (size_t)sp[i] * n, y, i0);
-      if (lane == 0) y[i] -= s;
+    if (i0 > 0) {
+      for (int i = i0 + 4 * wv; i < i1; i += 4 * RW) {
+        const T* rows[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rows[q] = L + (size_t)sp[min(i + q, i1 - 1)] * n;
+        double s[4];
+        wave_dot_rows<T, 4>(rows, y, i0, s);
+        if (lane < 4 && i + lane < i1) {
+          double v = s[0];
+#pragma unroll
+          for (int q = 1; q < 4; ++q) v = lane == q ? s[q] : v;
+          y[i + lane] -= v;
+        }
+      }
     }
     for (int q = tid; q < 64 * 64; q += RTHR) {
       const int rr = q / 64, cc = q % 64;
-      blk[rr * 65 + cc] = (rr < bw && cc < rr) ? (double)L[(size_t)sp[i0 + rr] * n + i0 + cc] : 0.0;
+      blk[rr * 65 + cc] = (rr < bw && cc < rr) ? L[(size_t)sp[i0 + rr] * n + i0 + cc] : T(0);
     }
     __syncthreads();
     if (wv == 0) {
       double yl = lane < bw ? y[i0 + lane] : 0.0;
       for (int k = 0; k < bw; ++k) {
         const double yk = __shfl(yl, k, kWave);
-        if (lane > k) yl -= blk[lane * 65 + k] * yk;
+        if (lane > k) yl -= (double)blk[lane * 65 + k] * yk;
       }
       if (lane < bw) y[i0 + lane] = yl;
     }
@@ -950,9 +965,18 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   }
   for (int i = tid; i < n; i += RTHR) w[(size_t)e * n + sp[i]] = y[i];
   const T* L2 = L21 + (size_t)e * t * n;
-  for (int i = wv; i < t; i += RTHR / 64) {
-    const double s = wave_dot<T>(L2 + (size_t)i * n, y, n);
-    if (lane == 0) r[(size_t)e * t + i] = -s;
+  for (int i = 4 * wv; i < t; i += 4 * RW) {
+    const T* rows[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rows[q] = L2 + (size_t)min(i + q, t - 1) * n;
+    double s[4];
+    wave_dot_rows<T, 4>(rows, y, n, s);
+    if (lane < 4 && i + lane < t) {
+      double v = s[0];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) v = lane == q ? s[q] : v;
+      r[(size_t)e * t + i + lane] = -v;
+    }
   }
 }
 
@@ -1001,13 +1025,15 @@ extern "C" iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense_rhs: bad sizes");
   if (n_elem == 0) return IEDG_OK;
   if (!LU || !perm || !L21 || !F || !w || !r) return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense_rhs: null pointer");
-  const size_t smem = sizeof(double) * (n_local + 64 * 65) + sizeof(int) * n_local;
+  const size_t smem0 = sizeof(double) * n_local + sizeof(int) * ((n_local + 3) & ~3);
   if (prec == IEDG_F64) {
+    const size_t smem = smem0 + sizeof(double) * 64 * 65;
     auto k = condense_rhs_kernel<double>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(n_elem), dim3(RTHR), smem, stream, n_local, n_trace_elem, (const double*)LU, perm,
                        (const double*)L21, F, w, r);
   } else if (prec == IEDG_F32 || prec == IEDG_BF16) {
+    const size_t smem = smem0 + sizeof(float) * 64 * 65;
     auto k = condense_rhs_kernel<float>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(n_elem), dim3(RTHR), smem, stream, n_local, n_trace_elem, (const float*)LU, perm,

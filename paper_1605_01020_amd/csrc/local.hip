@@ -10,6 +10,10 @@ constexpr int LWAVES = LTHR / 64;
 
 // z_e = U^{-1} (w_e - U12_e uhat_e): one workgroup per element.  Position i
 // of the factorisation lives in physical row perm[i] of LU, U12 and w.
+// Rows are processed four per wave at a time (wave_dot_rows) so each lane
+// keeps 16 loads in flight; 64-row diagonal blocks of U are staged in LDS in
+// the storage precision and solved by one wave.  LDS stays small so that
+// several elements share a CU.
 template <typename T>
 __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, const int32_t* elem_faces, const T* LU,
                                                          const int32_t* perm, const T* U12, const double* w,
@@ -17,8 +21,8 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* ue = reinterpret_cast<double*>(smem_raw);  // t
   double* y = ue + t;                                // n
-  double* blk = y + n;                               // 64 x 65
-  int* sp = reinterpret_cast<int*>(blk + 64 * 65);   // n
+  int* sp = reinterpret_cast<int*>(y + n);           // n
+  T* blk = reinterpret_cast<T*>(sp + ((n + 3) & ~3));  // 64 x 65
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < t; i += LTHR) {
     const int a = i / b, l = i % b;
@@ -27,9 +31,18 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
   for (int i = tid; i < n; i += LTHR) sp[i] = perm[(size_t)e * n + i];
   __syncthreads();
   const T* U12e = U12 + (size_t)e * n * t;
-  for (int i = wv; i < n; i += LWAVES) {
-    const double s = wave_dot<T>(U12e + (size_t)sp[i] * t, ue, t);
-    if (lane == 0) y[i] = w[(size_t)e * n + sp[i]] - s;
+  for (int i = 4 * wv; i < n; i += 4 * LWAVES) {
+    const T* rows[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rows[r] = U12e + (size_t)sp[min(i + r, n - 1)] * t;
+    double s[4];
+    wave_dot_rows<T, 4>(rows, ue, t, s);
+    if (lane < 4 && i + lane < n) {
+      double v = s[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) v = lane == r ? s[r] : v;
+      y[i + lane] = w[(size_t)e * n + sp[i + lane]] - v;
+    }
   }
   __syncthreads();
   const T* U = LU + (size_t)e * n * n;
@@ -37,21 +50,32 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int i0 = bi * 64, i1 = min(i0 + 64, n), bw = i1 - i0;
     // y[i0:i1] -= U[i0:i1, i1:n] z[i1:n]   (z stored in y beyond i1)
-    for (int i = i0 + wv; i < i1; i += LWAVES) {
-      const double s = wave_dot<T>(U + (size_t)sp[i] * n + i1, y + i1, n - i1);
-      if (lane == 0) y[i] -= s;
+    if (i1 < n) {
+      for (int i = i0 + 4 * wv; i < i1; i += 4 * LWAVES) {
+        const T* rows[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rows[r] = U + (size_t)sp[min(i + r, i1 - 1)] * n + i1;
+        double s[4];
+        wave_dot_rows<T, 4>(rows, y + i1, n - i1, s);
+        if (lane < 4 && i + lane < i1) {
+          double v = s[0];
+#pragma unroll
+          for (int r = 1; r < 4; ++r) v = lane == r ? s[r] : v;
+          y[i + lane] -= v;
+        }
+      }
     }
     for (int q = tid; q < 64 * 64; q += LTHR) {
       const int rr = q / 64, cc = q % 64;
-      blk[rr * 65 + cc] = (rr < bw && cc < bw && cc >= rr) ? (double)U[(size_t)sp[i0 + rr] * n + i0 + cc] : 0.0;
+      blk[rr * 65 + cc] = (rr < bw && cc < bw && cc >= rr) ? U[(size_t)sp[i0 + rr] * n + i0 + cc] : T(0);
     }
     __syncthreads();
     if (wv == 0) {
       double yl = lane < bw ? y[i0 + lane] : 0.0;
       for (int k = bw - 1; k >= 0; --k) {
-        const double zk = __shfl(yl, k, kWave) / blk[k * 65 + k];
+        const double zk = __shfl(yl, k, kWave) / (double)blk[k * 65 + k];
         if (lane == k) yl = zk;
-        if (lane < k) yl -= blk[lane * 65 + k] * zk;
+        if (lane < k) yl -= (double)blk[lane * 65 + k] * zk;
       }
       if (lane < bw) y[i0 + lane] = yl;
     }
@@ -156,13 +180,15 @@ extern "C" iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, in
                                             const double* uhat, double* z, hipStream_t stream) {
   if (!ctx || !mesh || !LU || !perm || !U12 || !w || !uhat || !z || n_local <= 0) return IEDG_ERR_INVALID_ARG;
   const int n = n_local, t = mesh->t, b = mesh->b;
-  const size_t smem = sizeof(double) * (t + n + 64 * 65) + sizeof(int) * n;
+  const size_t smem_ints = sizeof(double) * (t + n) + sizeof(int) * ((n + 3) & ~3);
   if (prec == IEDG_F64) {
+    const size_t smem = smem_ints + sizeof(double) * 64 * 65;
     auto k = backsolve_kernel<double>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
                        (const double*)LU, perm, (const double*)U12, w, uhat, z);
   } else {
+    const size_t smem = smem_ints + sizeof(float) * 64 * 65;
     auto k = backsolve_kernel<float>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,

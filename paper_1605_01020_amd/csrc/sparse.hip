@@ -353,7 +353,10 @@ __device__ inline void lds_block_mm(int b, const T* sA, const T* sB, typename Mf
   }
 }
 
-template <typename T>
+// STAGE_C: the block being updated is staged in LDS too (three b x b buffers);
+// otherwise (large b) the update is applied to it in global memory in the
+// accumulator layout and two buffers suffice.
+template <typename T, bool STAGE_C>
 __global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32_t* rows, const int32_t* diag_slot,
                                                               const int32_t* lptr, const int32_t* lslot,
                                                               const int32_t* uptr, const int32_t* upd, T* M,
@@ -363,8 +366,8 @@ __global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32
   const int ls = b + 1;
   T* sX = reinterpret_cast<T*>(smem_raw);   // b x ls: A_ik, then L_ik
   T* sB = sX + (size_t)b * ls;              // b x ls: right operand
-  T* sC = sB + (size_t)b * ls;              // b x ls: block being updated
-  int* piv = reinterpret_cast<int*>(sC + (size_t)b * ls);
+  T* sC = sB + (size_t)b * ls;              // b x ls: block being updated (STAGE_C)
+  int* piv = reinterpret_cast<int*>(STAGE_C ? sC + (size_t)b * ls : sC);
   double* rv = reinterpret_cast<double*>(piv + 128);
   int* ri = reinterpret_cast<int*>(rv + 1);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15;
@@ -395,7 +398,12 @@ __global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32
     for (int q = threadIdx.x; q < (int)bb; q += STHR) M[sik * bb + q] = sX[(q / b) * ls + q % b];
     for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
       const int skj = upd[2 * u], sij = upd[2 * u + 1];
-      lds_block_load2<T>(M + skj * bb, sB, M + sij * bb, sC, b);
+      T* C = M + sij * bb;
+      if constexpr (STAGE_C) {
+        lds_block_load2<T>(M + skj * bb, sB, C, sC, b);
+      } else {
+        lds_block_load2<T>(M + skj * bb, sB, nullptr, nullptr, b);
+      }
       __syncthreads();
       lds_block_mm<T>(b, sX, sB, acc);
 #pragma unroll
@@ -406,24 +414,33 @@ __global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int r = i0 + MF::row(lane, v), c = j0 + li;
-            if (r < b && c < b) sC[c * ls + r] -= acc[q][v];
+            if (r < b && c < b) {
+              if constexpr (STAGE_C)
+                sC[c * ls + r] -= acc[q][v];
+              else
+                C[(size_t)c * b + r] -= acc[q][v];
+            }
           }
         }
       }
-      __syncthreads();
-      T* C = M + sij * bb;
-      for (int q = threadIdx.x; q < (int)bb; q += STHR) C[q] = sC[(q / b) * ls + q % b];
-      __syncthreads();
+      if constexpr (STAGE_C) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < (int)bb; q += STHR) C[q] = sC[(q / b) * ls + q % b];
+        __syncthreads();
+      } else {
+        sync_global();  // sB is reloaded next; C may be updated again
+      }
     }
     sync_global();
   }
   // pivot block: invert in place (row-major staging in sX)
   T* Dg = M + diag_slot[i] * bb;
-  lds_block_load2<T>(Dg, sC, nullptr, nullptr, b);
+  T* sD = STAGE_C ? sC : sB;
+  lds_block_load2<T>(Dg, sD, nullptr, nullptr, b);
   __syncthreads();
   for (int q = threadIdx.x; q < (int)bb; q += STHR) {
     const int c = q / b, r = q % b;
-    sX[r * ls + c] = sC[c * ls + r];
+    sX[r * ls + c] = sD[c * ls + r];
   }
   __syncthreads();
   const bool ok = gj_invert<T>(sX, b, piv, rv, ri);
@@ -521,22 +538,28 @@ iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh m, iedg_prec prec, cons
   if (Kbsr != Mbsr)
     IEDG_HIP(ctx, hipMemcpyAsync(Mbsr, Kbsr, es * m->nnzb * m->b * m->b, hipMemcpyDeviceToDevice, stream));
   const size_t smem = es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
-  const size_t smem2 = 3 * es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
-  const bool staged = smem2 <= 160 * 1024;
+  const size_t tail = sizeof(int) * 128 + 2 * sizeof(double);
+  const size_t smem3 = 3 * es * m->b * (m->b + 1) + tail, smem2 = 2 * es * m->b * (m->b + 1) + tail;
+  const int mode = smem3 <= 160 * 1024 ? 3 : (smem2 <= 160 * 1024 ? 2 : 0);
   for (int l = 0; l < m->n_levels; ++l) {
     const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
-    if (staged) {
-      if (prec == IEDG_F64) {
-        auto k = ilu0_level_lds_kernel<double>;
-        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem2));
-        hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem2, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
-                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (double*)Mbsr, ctx->d_status);
-      } else {
-        auto k = ilu0_level_lds_kernel<float>;
-        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem2));
-        hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem2, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
-                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (float*)Mbsr, ctx->d_status);
-      }
+    if (mode) {
+      const size_t sm = mode == 3 ? smem3 : smem2;
+      auto launch = [&](auto kern, auto* Mp) -> iedg_status {
+        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+        hipLaunchKernelGGL(kern, dim3(cnt), dim3(STHR), sm, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, Mp, ctx->d_status);
+        return IEDG_OK;
+      };
+      iedg_status st;
+      if (prec == IEDG_F64)
+        st = mode == 3 ? launch(ilu0_level_lds_kernel<double, true>, (double*)Mbsr)
+                       : launch(ilu0_level_lds_kernel<double, false>, (double*)Mbsr);
+      else
+        st = mode == 3 ? launch(ilu0_level_lds_kernel<float, true>, (float*)Mbsr)
+                       : launch(ilu0_level_lds_kernel<float, false>, (float*)Mbsr);
+      if (st != IEDG_OK) return st;
       IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
       continue;
     }

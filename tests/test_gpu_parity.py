@@ -368,3 +368,34 @@ def test_config0_mixed_bf16_refinement(ctx, cfg0_oracle):
     assert info["converged_full"], info
     assert rel(uhat.cpu().numpy(), ref["uhat"]) <= 1e-7
     assert rel(z.cpu().numpy(), np.stack(ref["z"])) <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ilu0_large_blocks(ctx, prec):
+    """b = 125 (p = 4): FP32 blocks use the two-buffer LDS kernel (the block
+    being updated stays in global memory), FP64 blocks the unstaged kernel.
+    Tolerances: FP64 as above; FP32 blocks 2e-5 relative (unit roundoff 6e-8
+    over chains of block products of order 125)."""
+    m, spec, blocks, G = host_case((2, 1, 1), 4)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec)
+    q = mesh.query()
+    Ks, rs = oracle.condense_all(blocks)
+    K, R = oracle.assemble(tm, Ks, rs, G)
+    _say(f"ilu0 b=125 prec={prec}")
+    Kd = dev(bsr_from_oracle(mesh, K, q))
+    if prec == 1:
+        Kd = Kd.float()
+    Md = api.factor_ilu0(ctx, mesh, Kd, prec=prec)
+    ctx.sync_status()
+    fac = oracle.bilu0(tm, K, q["order"])
+    got = oracle_from_bsr(mesh, Md.double().cpu().numpy(), q)
+    tol = 1e-11 if prec == 0 else 2e-5
+    scale = max(np.abs(v).max() for v in K.values())
+    for key, Lb in fac["L"].items():
+        assert np.abs(got[key] - Lb).max() <= tol * scale, key
+    for key, Ub in fac["U"].items():
+        if key[0] != key[1]:
+            assert np.abs(got[key] - Ub).max() <= tol * scale, key
+    for i, Ui in fac["Uinv"].items():
+        assert np.abs(got[(i, i)] - Ui).max() <= tol * np.abs(Ui).max(), i

@@ -66,17 +66,27 @@ struct Elem {
   double *w, *r;
   const int* sperm;
 
+  // Input value at (row, col).  FP32 storage: A, B, C, D were first copied
+  // (converted) into the output arrays, whose entries are read exactly once
+  // as input before they are overwritten (Crout order), so the input is read
+  // there in the storage type -- no conversion stands between the load and
+  // the MFMA accumulators it initialises.
   __device__ __attribute__((always_inline)) T in(int row, int col) const {
-    if (row < n) {
-      const size_t pr = (size_t)sperm[row];
-      if (col < n) return (T)A[pr * n + col];
-      if (col < N) return (T)B[pr * t + (col - n)];
-      return (T)F[pr];
+    if constexpr (sizeof(T) == 4) {
+      if (col < N) return ld(row, col);
+      return row < n ? (T)F[sperm[row]] : T(0);
+    } else {
+      if (row < n) {
+        const size_t pr = (size_t)sperm[row];
+        if (col < n) return (T)A[pr * n + col];
+        if (col < N) return (T)B[pr * t + (col - n)];
+        return (T)F[pr];
+      }
+      const size_t q = (size_t)(row - n);
+      if (col < n) return (T)C[q * n + col];
+      if (col < N) return (T)D[q * t + (col - n)];
+      return T(0);
     }
-    const size_t q = (size_t)(row - n);
-    if (col < n) return (T)C[q * n + col];
-    if (col < N) return (T)D[q * t + (col - n)];
-    return T(0);
   }
   __device__ __attribute__((always_inline)) T ld(int row, int col) const {
     if (row < n) {
@@ -114,8 +124,9 @@ template <> struct Pair<double> { typedef double2 v; };
 template <> struct Pair<float> { typedef float2 v; };
 
 // ---- GEMM engine ----------------------------------------------------------
-// acc = L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN tile;
-// rows >= rlim, cols >= clim and k >= K read as zero.  Waves are stacked
+// acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
+// tile (in = the bordered matrix's input values); rows >= rlim, cols >= clim
+// and k >= K read as zero.  Waves are stacked
 // along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
 // wave 64 x 32).  k-slabs of KC are staged in two LDS buffers; each thread
 // keeps two slabs of global loads in flight.
@@ -208,9 +219,11 @@ struct SlabLoader {
     T* Bs = stage + KC * TL::SA;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
+      // L enters negated: the accumulators start from the tile's input
+      // values, so the MFMA chain computes in - L U directly
       const bool ok = aok[q] && k0 + ak[q] < K;
-      As[ak[q] * TL::SA + arow[q]] = ok ? va[q].x : T(0);
-      As[(ak[q] + 1) * TL::SA + arow[q]] = ok ? va[q].y : T(0);
+      As[ak[q] * TL::SA + arow[q]] = ok ? -va[q].x : T(0);
+      As[(ak[q] + 1) * TL::SA + arow[q]] = ok ? -va[q].y : T(0);
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) {
@@ -284,8 +297,10 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
   }
 }
 
-// acc = L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN tile;
-// rows >= rlim, cols >= clim and k >= K read as zero.  Waves are stacked
+// acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
+// tile; rows >= rlim, cols >= clim and k >= K read as zero.  The accumulators
+// start from the input values (read while the first slabs are in flight) and
+// L enters the MFMAs negated.  Waves are stacked
 // along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
 // wave 64 x 32).  k-slabs of KC go through two LDS stages; each thread keeps
 // the global loads of the next two slabs in flight in two register buffers.
@@ -299,11 +314,19 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   typedef typename Pair<T>::v P2;
   const int wv = threadIdx.x >> 6;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
+  const int lane = threadIdx.x & 63;
+  if (K <= 0) {
 #pragma unroll
-  for (int rb = 0; rb < TL::RB; ++rb)
+    for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < TL::CB; ++cb) acc[rb][cb] = MF::zero();
-  if (K <= 0) return;
+      for (int cb = 0; cb < TL::CB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = r0 + wr0 + 16 * rb + MF::row(lane, v), col = c0 + wc0 + 16 * cb + (lane & 15);
+          acc[rb][cb][v] = (row < rlim && col < clim) ? el.in(row, col) : T(0);
+        }
+    return;
+  }
   const int nch = (K + KC - 1) / KC;
   SlabLoader<T, TM, TN, HASW> ld;
   ld.init(el, r0, rlim, c0, clim, K);
@@ -316,6 +339,16 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   // before a store covers exactly the slab being stored
   ld.load(0, a0, b0, w0);
   ld.load(1, a1, b1, w1);
+  // the tile's input values, read while the first slabs are in flight
+#pragma unroll
+  for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < TL::CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + wr0 + 16 * rb + MF::row(lane, v), col = c0 + wc0 + 16 * cb + (lane & 15);
+        acc[rb][cb][v] = (row < rlim && col < clim) ? el.in(row, col) : T(0);
+      }
   ld.store(0, S0, a0, b0, w0);
   ld.load(2, a0, b0, w0);
   __syncthreads();
@@ -720,6 +753,26 @@ struct CondenseSmem {
   }
 };
 
+// dst[0:len] = (float) src[0:len] by the workgroup; len a multiple of 4,
+// 16 values per thread in flight.
+__device__ __attribute__((always_inline)) inline void convert_copy(const double* __restrict__ src,
+                                                                   float* __restrict__ dst, size_t len) {
+  const size_t step = (size_t)NT * 16;
+  for (size_t i0 = (size_t)threadIdx.x * 4; i0 < len; i0 += step) {
+    double4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t i = i0 + (size_t)u * NT * 4;
+      if (i < len) v[u] = *reinterpret_cast<const double4*>(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const size_t i = i0 + (size_t)u * NT * 4;
+      if (i < len) *reinterpret_cast<float4*>(dst + i) = make_float4((float)v[u].x, (float)v[u].y, (float)v[u].z, (float)v[u].w);
+    }
+  }
+}
+
 template <typename T, int QA, int QC, int LW, int MM>
 __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
   typedef Mfma<T> MF;
@@ -748,7 +801,15 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
   const int NC = el.NC;
 
   for (int i = tid; i < n; i += NT) sperm[i] = i;
-  __syncthreads();
+  if constexpr (sizeof(T) == 4) {
+    convert_copy(el.A, el.LU, nn);
+    convert_copy(el.B, el.U12, nt);
+    convert_copy(el.C, el.L21, nt);
+    convert_copy(el.D, el.Ke, tt);
+    sync_global();  // read by other threads below
+  } else {
+    __syncthreads();
+  }
 
   typedef Tile<T, 256, 64> TA;
   typedef Tile<T, 64, 256> TB;
@@ -759,7 +820,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
       typename MF::acc_t acc[TA::RB][TA::CB];
       gemm_tile<T, 256, 64, MM>(el, r0, N, c0, c1, c0, sg, acc);
       for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
-        if (row < N && col < c1) el.st(row, col, el.in(row, col) - v);
+        if (row < N && col < c1) el.st(row, col, v);
       });
     }
     sync_global();
@@ -784,7 +845,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
       else
         gemm_tile<T, 64, 256, MM, false>(el, c0, c1, j0, jl, c0, sg, acc);
       map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
-        return (row < c1 && col < jl) ? el.in(row, col) - v : T(0);
+        return (row < c1 && col < jl) ? v : T(0);
       });
       {
         const int lane = tid & 63, li = lane & 15;
@@ -821,7 +882,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
       else
         gemm_tile<T, 256, 64, MM, false>(el, r0, N, j0, jl, n, sg, acc);
       for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
-        if (row < N && col < jl) el.st(row, col, el.in(row, col) - v);
+        if (row < N && col < jl) el.st(row, col, v);
       });
     }
   }

@@ -63,7 +63,7 @@ class Simulation:
     buffers of the solve and of its refinement."""
 
     def __init__(self, ctx, case, seed, prec=F32, restart=100, n_refine=1, tol=1e-8, inner_rtol=1e-6,
-                 correction_rtol=1e-3, ordering="colour", cycle_steps=40):
+                 correction_rtol=1e-3, ordering="colour", cycle_steps=24):
         from synth.mesh import StructuredHexMesh
         self.ctx, self.case, self.seed, self.prec = ctx, case, seed, prec
         self.tol, self.inner_rtol, self.correction_rtol = tol, inner_rtol, correction_rtol

@@ -76,14 +76,25 @@ __device__ inline double block_row_sum(int b, const T* blocks, const int32_t* co
   for (int s = s0 + g; s < s1; s += G) {
     const T* blk = blocks + (size_t)s * b * b + rr;
     const double* xs = x + (size_t)col_face[s] * b;
+    // eight columns per round trip: eight block loads (contiguous across the
+    // group's lanes) and eight vector loads in flight per lane
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = 0.0;
     int cc = 0;
-    double a0 = 0.0, a1 = 0.0;
-    for (; cc + 1 < b; cc += 2) {
-      a0 += (double)blk[(size_t)cc * b] * xs[cc];
-      a1 += (double)blk[(size_t)(cc + 1) * b] * xs[cc + 1];
+    for (; cc + 8 <= b; cc += 8) {
+      T m[8];
+      double xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        m[u] = blk[(size_t)(cc + u) * b];
+        xv[u] = xs[cc + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += (double)m[u] * xv[u];
     }
-    if (cc < b) a0 += (double)blk[(size_t)cc * b] * xs[cc];
-    acc += a0 + a1;
+    for (; cc < b; ++cc) a[0] += (double)blk[(size_t)cc * b] * xs[cc];
+    acc += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   }
   return acc;
 }
@@ -147,7 +158,17 @@ __global__ __launch_bounds__(STHR) void sweep_kernel(int b, const int32_t* rows,
   double acc = 0.0;
   if (g < G) {
     const T* blk = M + (size_t)ds * b * b + rr;
-    for (int cc = g; cc < b; cc += G) acc += (double)blk[(size_t)cc * b] * svec[cc];
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int cc = g;
+    for (; cc + 3 * G < b; cc += 4 * G) {
+      T m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) m[u] = blk[(size_t)(cc + u * G) * b];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += (double)m[u] * svec[cc + u * G];
+    }
+    for (; cc < b; cc += G) a[0] += (double)blk[(size_t)cc * b] * svec[cc];
+    acc = (a[0] + a[1]) + (a[2] + a[3]);
   }
   group_reduce(red, b, G, g, rr, acc);
   if (threadIdx.x < b) y[o + threadIdx.x] = red[G * b + threadIdx.x];

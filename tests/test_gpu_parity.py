@@ -3,6 +3,7 @@ inputs.  Tolerances follow the FP64 rounding of each step (documented in the
 design notes): element Schur complements and right-hand sides <= 1e-12
 relative, assembly bit-exact, BILU(0) factors <= 1e-11, products <= 1e-13,
 solutions within condition * rtol."""
+import ctypes
 import sys
 
 import numpy as np
@@ -399,3 +400,72 @@ def test_ilu0_large_blocks(ctx, prec):
             assert np.abs(got[key] - Ub).max() <= tol * scale, key
     for i, Ui in fac["Uinv"].items():
         assert np.abs(got[(i, i)] - Ui).max() <= tol * np.abs(Ui).max(), i
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_condense_largest_elements(ctx, prec):
+    """p = 4 elements (n = 2,500, t = 750: five A rows and two C rows per
+    thread, 40 panels with a 4-wide last one) in every precision, with both
+    sub-panel widths."""
+    from paper_1605_01020_amd import F64, F32, BF16
+    m, spec, blocks, G = host_case((2, 1, 1), 4, seed=SEED_BASE + 9)
+    d = host_blocks_to_dev(blocks)
+    refs = [oracle.condense_element(b_["A"], b_["B"], b_["C"], b_["D"], b_["F"]) for b_ in blocks]
+    for lw in (8, 16):
+        api.set_leaf_width(ctx, spec.n, lw, prec=F64 if prec == 0 else F32)
+        _say(f"condense p=4 prec={prec} sub-panel {lw}")
+        fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=prec)
+        ctx.sync_status()
+        for e, (Ke, re, _) in enumerate(refs):
+            ke = fac["Ke"][e].double().cpu().numpy()
+            rr = fac["r"][e].cpu().numpy()
+            if prec == 0:
+                assert rel(ke, Ke) <= 1e-12 and rel(rr, re) <= 1e-12
+            elif prec == 1:
+                assert rel(ke, Ke) <= 2e-5 and rel(rr, re) <= 2e-5
+            else:
+                corr = np.linalg.norm(blocks[e]["D"] - Ke)
+                assert np.linalg.norm(ke - Ke) <= 2.0 ** -6 * corr + 2e-5 * np.linalg.norm(Ke)
+                assert rel(rr, re) <= 2.0 ** -6
+    # back to the tuned width
+    from paper_1605_01020_amd.autotune import apply_tuning
+    apply_tuning(ctx)
+
+
+def test_argument_errors(ctx):
+    """Argument checks return before anything is enqueued."""
+    from paper_1605_01020_amd import F64
+    L = ctx.L
+    z = torch.zeros(16, dtype=torch.float64, device="cuda")
+    i32 = torch.zeros(16, dtype=torch.int32, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    s0 = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    # empty batch: nothing to do
+    assert L.iedg_condense(ctx.h, 0, 540, 270, F64, p(z), p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == 0
+    # n not a multiple of 4, t odd: unsupported
+    assert L.iedg_condense(ctx.h, 1, 6, 4, F64, p(z), p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -7
+    assert L.iedg_condense(ctx.h, 1, 8, 3, F64, p(z), p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -7
+    # null input, F without w and r, bad precision
+    assert L.iedg_condense(ctx.h, 1, 8, 4, F64, None, p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -1
+    assert L.iedg_condense(ctx.h, 1, 8, 4, F64, p(z), p(z), p(z), p(z), p(z), p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -1
+    assert L.iedg_condense(ctx.h, 1, 8, 4, 7, p(z), p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -7
+    # sub-panel width, GMRES restart and state size
+    assert L.iedg_set_leaf_width(ctx.h, F64, 1280, 4) == -1
+    m, spec, blocks, G = host_case((1, 1, 1), 1)
+    mesh = _mesh(ctx, m, spec)
+    h = ctypes.c_void_p()
+    assert L.iedg_gmres_state_create(ctx.h, mesh.h, 0, ctypes.byref(h)) == -1
+    with pytest.raises(api.IedgError):
+        api.gmres_solve(ctx, mesh, z, z, z, restart=0, rtol=1e-10)
+    # a face id outside [0, n_face) is rejected by the mesh builder
+    ef = m.elem_faces().copy()
+    ef[0, 0] = m.n_face
+    with pytest.raises(api.IedgError):
+        api.Mesh(ctx, ef, m.n_face, spec.b)
+    assert ctx.L.iedg_last_error(ctx.h)

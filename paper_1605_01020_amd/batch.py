@@ -99,7 +99,9 @@ class Simulation:
         # device-driven cycles stop at cycle_steps Arnoldi steps (every step
         # is enqueued, later ones return at once after convergence); a cycle
         # that stops unconverged is continued by the refinement on the host
-        self.gm = [api.GmresState(ctx, self.mesh, min(restart, cycle_steps)) for _ in range(n_refine + 1)]
+        # (corrections at tolerance 1e-3 need a few steps: half the cap)
+        self.gm = [api.GmresState(ctx, self.mesh, min(restart, cycle_steps if s == 0 else max(8, cycle_steps // 2)))
+                   for s in range(n_refine + 1)]
         self.restart = restart
 
     @staticmethod

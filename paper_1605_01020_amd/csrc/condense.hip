@@ -648,8 +648,12 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       }
       // eliminate below the pivot: registers 1 .. sw-kk-1 are the columns
       // right of k in this sub-panel (the others hold finished columns)
+      // (the pivot row is masked once, so finished columns take l * 0)
       const T rinv = T(1) / u[0];
       const int live = sw - kk;
+      T um[SW];
+#pragma unroll
+      for (int j = 1; j < SW; ++j) um[j] = j < live ? u[j] : T(0);
 #pragma unroll
       for (int q = 0; q < QA; ++q) {
         const int p = c0 + tid + NT * q;
@@ -657,8 +661,7 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
           const T l = x[q][0] * rinv;
           x[q][0] = l;
 #pragma unroll
-          for (int j = 1; j < SW; ++j)
-            if (j < live) x[q][j] -= l * u[j];
+          for (int j = 1; j < SW; ++j) x[q][j] -= l * um[j];
         }
       }
 #pragma unroll
@@ -667,8 +670,7 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
           const T l = xc[q][0] * rinv;
           xc[q][0] = l;
 #pragma unroll
-          for (int j = 1; j < SW; ++j)
-            if (j < live) xc[q][j] -= l * u[j];
+          for (int j = 1; j < SW; ++j) xc[q][j] -= l * um[j];
         }
       }
       rotate_rows<T, QA, QC, SW>(x, xc);

@@ -120,6 +120,10 @@ class Server:
             self.stats["evictions"] += 1
             del sim
         assert self.used + need <= self.budget
+        # evicted simulations' blocks stay in torch's cache; give them back
+        # when the cache has grown well past the budget (limits fragmentation)
+        if torch.cuda.memory_reserved() > 1.25 * self.budget:
+            torch.cuda.empty_cache()
         sim = Simulation(self.ctx, self.cases[sid], self.seed, prec=self.prec, restart=self.restart,
                          n_refine=self.n_refine, tol=self.tol)
         self.resident[sid] = sim

@@ -161,7 +161,7 @@ def alloc_condense_out(E, n, t, prec, device, with_rhs=True):
 
 
 class CondenseBatch:
-    """Plan for one persistent condensation launch over several segments
+    """Plan for one condensation launch over several segments
     (meshes) with the same element size (iedg_batch_*).  `segments` is a
     list of (inputs, outputs) dicts: inputs A, B, C, D, F (F may be None),
     outputs as from alloc_condense_out.  Tensors must outlive the plan."""

@@ -230,7 +230,7 @@ def _nnzb_estimate(hm):
 
 
 class BatchGroup:
-    """Meshes solved together: one persistent condensation launch per element
+    """Meshes solved together: one condensation launch per element
     size, then every mesh's trace solve; optionally captured in a graph."""
 
     def __init__(self, ctx, sims):

@@ -38,6 +38,59 @@ __device__ __attribute__((always_inline)) inline T opaque(T v) {
   return v;
 }
 
+// Wave-wide maximum and minimum without a round trip through LDS: two quad
+// permutations and two rotations inside each 16-lane row (DPP) leave the
+// row's extremum in every lane of the row; the four rows are then read as
+// uniform values.  The result is the same in every lane.
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRor4 = 0x124;  // row_ror:4
+constexpr int kDppRor8 = 0x128;  // row_ror:8
+
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline float dpp_move(float v) {
+  return __int_as_float(dpp_i32<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline double dpp_move(double v) {
+  return __hiloint2double(dpp_i32<CTRL>(__double2hiint(v)), dpp_i32<CTRL>(__double2loint(v)));
+}
+template <int CTRL>
+__device__ __attribute__((always_inline)) inline int dpp_move(int v) {
+  return dpp_i32<CTRL>(v);
+}
+__device__ __attribute__((always_inline)) inline float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __attribute__((always_inline)) inline double read_lane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __attribute__((always_inline)) inline int read_lane(int v, int l) {
+  return __builtin_amdgcn_readlane(v, l);
+}
+
+// (values must not be NaN)
+template <typename T>
+__device__ __attribute__((always_inline)) inline T wave_max(T v) {
+  v = fmax(v, dpp_move<kDppXor1>(v));
+  v = fmax(v, dpp_move<kDppXor2>(v));
+  v = fmax(v, dpp_move<kDppRor4>(v));
+  v = fmax(v, dpp_move<kDppRor8>(v));
+  return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
+}
+__device__ __attribute__((always_inline)) inline int wave_min(int v) {
+  v = min(v, dpp_move<kDppXor1>(v));
+  v = min(v, dpp_move<kDppXor2>(v));
+  v = min(v, dpp_move<kDppRor4>(v));
+  v = min(v, dpp_move<kDppRor8>(v));
+  return min(min(read_lane(v, 0), read_lane(v, 16)), min(read_lane(v, 32), read_lane(v, 48)));
+}
+
 
 constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
@@ -580,13 +633,10 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
         if (p >= k && p < n && v > best) { best = v; bq = q; }
       }
       const int mine = bq >= 0 ? c0 + tid + NT * bq : INT_MAX;
-      int bidx = mine;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ov = __shfl_xor(best, off, kWave);
-        const int oi = __shfl_xor(bidx, off, kWave);
-        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-      }
+      // the wave's candidate: largest magnitude, ties to the smallest
+      // position (best is -1 where a thread has none, never NaN)
+      const T wbest = wave_max(best);
+      int bidx = wave_min(best == wbest ? mine : INT_MAX);
       // (register rows are chosen with value selects, never through a
       // pointer to a row, so that they stay in registers)
       T* cw = pb.cand + (par * NW + wv) * SW;
@@ -595,11 +645,16 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
         for (int j = 0; j < SW; ++j) {
           T v = x[0][j];
 #pragma unroll
-          for (int q = 1; q < QA; ++q) v = (q == bq) ? opaque(x[q][j]) : v;
+          for (int q = 1; q < QA; ++q) {
+            // (taken out of the select, so that it becomes a move and a
+            // v_cndmask rather than a branch around the volatile asm)
+            const T o = opaque(x[q][j]);
+            v = (q == bq) ? o : v;
+          }
           cw[j] = v;
         }
       }
-      if (lane == 0) { pb.ps->cv[par][wv] = (double)best; pb.ps->ci[par][wv] = bidx; }
+      if (lane == 0) { pb.ps->cv[par][wv] = (double)wbest; pb.ps->ci[par][wv] = bidx; }
       const int ko = k - c0;  // owner of position k: thread ko (slot 0, ko < CT <= NT)
       const bool own_k = tid == ko;
       T* kr = pb.krow + par * SW;
@@ -615,7 +670,11 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       for (int i = 1; i < NW; ++i) {
         const double ov = pb.ps->cv[par][i];
         const int oi = pb.ps->ci[par][i];
-        if (ov > gbest || (ov == gbest && oi < bidx)) { gbest = ov; bidx = oi; bw = i; }
+        // (bitwise operators: no short-circuit branches)
+        const bool take = (ov > gbest) | ((ov == gbest) & (oi < bidx));
+        gbest = take ? ov : gbest;
+        bidx = take ? oi : bidx;
+        bw = take ? i : bw;
       }
       int piv = bidx;
       const T* urow = pb.cand + (par * NW + bw) * SW;

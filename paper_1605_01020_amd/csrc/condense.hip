@@ -637,22 +637,17 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       // position (best is -1 where a thread has none, never NaN)
       const T wbest = wave_max(best);
       int bidx = wave_min(best == wbest ? mine : INT_MAX);
-      // (register rows are chosen with value selects, never through a
-      // pointer to a row, so that they stay in registers)
+      // (register rows are named in static branches on the slot, never
+      // reached through a pointer to a row, so that they stay in registers;
+      // one lane of the wave is active, so one branch runs)
       T* cw = pb.cand + (par * NW + wv) * SW;
       if (mine == bidx && bidx != INT_MAX) {
 #pragma unroll
-        for (int j = 0; j < SW; ++j) {
-          T v = x[0][j];
+        for (int q = 0; q < QA; ++q)
+          if (q == bq) {
 #pragma unroll
-          for (int q = 1; q < QA; ++q) {
-            // (taken out of the select, so that it becomes a move and a
-            // v_cndmask rather than a branch around the volatile asm)
-            const T o = opaque(x[q][j]);
-            v = (q == bq) ? o : v;
+            for (int j = 0; j < SW; ++j) cw[j] = x[q][j];
           }
-          cw[j] = v;
-        }
       }
       if (lane == 0) { pb.ps->cv[par][wv] = (double)wbest; pb.ps->ci[par][wv] = bidx; }
       const int ko = k - c0;  // owner of position k: thread ko (slot 0, ko < CT <= NT)
@@ -689,16 +684,19 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       const int po = piv - c0;
       const bool own_p = piv != k && tid == po % NT;
       const int sp = po / NT;
-      if (own_p || own_k) {
+      // the interchange (a thread owning both positions holds k in slot 0
+      // and the pivot row in a later slot)
+      if (own_k) {
 #pragma unroll
-        for (int j = 0; j < SW; ++j) {
-          const T kv = kr[j];
+        for (int j = 0; j < SW; ++j) x[0][j] = u[j];
+      }
+      if (own_p) {
 #pragma unroll
-          for (int q = 0; q < QA; ++q) {
-            T v = (own_p && q == sp) ? kv : x[q][j];
-            x[q][j] = (own_k && q == 0) ? u[j] : v;
+        for (int q = 0; q < QA; ++q)
+          if (q == sp) {
+#pragma unroll
+            for (int j = 0; j < SW; ++j) x[q][j] = kr[j];
           }
-        }
       }
       if (tid == 0 && piv != k) {
         const int tmp = sperm[k];

@@ -29,15 +29,6 @@
 
 namespace iedg {
 
-// A value the optimiser cannot trace back to the register array it came
-// from: a select between such values is never rewritten into a load through
-// a selected address (which would demote the array to scratch memory).
-template <typename T>
-__device__ __attribute__((always_inline)) inline T opaque(T v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
 // Wave-wide maximum and minimum without a round trip through LDS: two quad
 // permutations and two rotations inside each 16-lane row (DPP) leave the
 // row's extremum in every lane of the row; the four rows are then read as

@@ -495,6 +495,20 @@ __device__ __attribute__((always_inline)) inline void rotate_rows(T (&x)[QA][SW]
   }
 }
 
+// A register row moved as 16-byte vectors (the caller guarantees alignment).
+template <typename T, int W>
+__device__ __attribute__((always_inline)) inline void load_row16(T (&dst)[W], const T* src) {
+  const T* s = static_cast<const T*>(__builtin_assume_aligned(src, 16));
+#pragma unroll
+  for (int j = 0; j < W; ++j) dst[j] = s[j];
+}
+template <typename T, int W>
+__device__ __attribute__((always_inline)) inline void store_row16(T* dst, const T (&src)[W]) {
+  T* d = static_cast<T*>(__builtin_assume_aligned(dst, 16));
+#pragma unroll
+  for (int j = 0; j < W; ++j) d[j] = src[j];
+}
+
 template <typename T, int QA, int QC, int SW>
 __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1,
                                                             const PanelBufs<T>& pb, DeviceStatus* status, int elem) {
@@ -502,6 +516,11 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
   constexpr int KCH = PS::KCH;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = el.n, N = el.N;
+  // every row of LU and L21 starts on a 16-byte boundary (and so does every
+  // sub-panel and chunk below, at multiples of 4 columns): full rows of a
+  // sub-panel then move as 16-byte vectors
+  const bool vec = (n * sizeof(T)) % 16 == 0 &&
+                   ((reinterpret_cast<uintptr_t>(el.LU) | reinterpret_cast<uintptr_t>(el.L21)) & 15) == 0;
   for (int cs = c0; cs < c1; cs += SW) {
     const int sw = min(SW, c1 - cs), kp = cs - c0;
     // the previous sub-panel's stores are read below by other threads (rows
@@ -524,15 +543,25 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       const int r = n + tid + NT * q;
       xrc[q] = r < N ? el.lrow(r) + cs : nullptr;
     }
-    if (sw == SW) {
+    if (sw == SW && vec) {
 #pragma unroll
-      for (int q = 0; q < QA; ++q)
+      for (int q = 0; q < QA; ++q) {
+        if (xra[q]) {
+          load_row16(x[q], xra[q]);
+        } else {
 #pragma unroll
-        for (int j = 0; j < SW; ++j) x[q][j] = xra[q] ? xra[q][j] : T(0);
+          for (int j = 0; j < SW; ++j) x[q][j] = T(0);
+        }
+      }
 #pragma unroll
-      for (int q = 0; q < QC; ++q)
+      for (int q = 0; q < QC; ++q) {
+        if (xrc[q]) {
+          load_row16(xc[q], xrc[q]);
+        } else {
 #pragma unroll
-        for (int j = 0; j < SW; ++j) xc[q][j] = xrc[q] ? xrc[q][j] : T(0);
+          for (int j = 0; j < SW; ++j) xc[q][j] = T(0);
+        }
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < QA; ++q)
@@ -578,14 +607,35 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       }
       for (int k0 = 0; k0 < kp; k0 += KCH) {
         T la[QA][KCH], lc[QC][KCH];
+        if (vec && k0 + KCH <= kp) {
 #pragma unroll
-        for (int q = 0; q < QA; ++q)
+          for (int q = 0; q < QA; ++q) {
+            if (lra[q]) {
+              load_row16(la[q], lra[q] + k0);
+            } else {
 #pragma unroll
-          for (int kk = 0; kk < KCH; ++kk) la[q][kk] = (lra[q] && k0 + kk < kp) ? lra[q][k0 + kk] : T(0);
+              for (int kk = 0; kk < KCH; ++kk) la[q][kk] = T(0);
+            }
+          }
 #pragma unroll
-        for (int q = 0; q < QC; ++q)
+          for (int q = 0; q < QC; ++q) {
+            if (lrc[q]) {
+              load_row16(lc[q], lrc[q] + k0);
+            } else {
 #pragma unroll
-          for (int kk = 0; kk < KCH; ++kk) lc[q][kk] = (lrc[q] && k0 + kk < kp) ? lrc[q][k0 + kk] : T(0);
+              for (int kk = 0; kk < KCH; ++kk) lc[q][kk] = T(0);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < QA; ++q)
+#pragma unroll
+            for (int kk = 0; kk < KCH; ++kk) la[q][kk] = (lra[q] && k0 + kk < kp) ? lra[q][k0 + kk] : T(0);
+#pragma unroll
+          for (int q = 0; q < QC; ++q)
+#pragma unroll
+            for (int kk = 0; kk < KCH; ++kk) lc[q][kk] = (lrc[q] && k0 + kk < kp) ? lrc[q][k0 + kk] : T(0);
+        }
 #pragma unroll
         for (int kk = 0; kk < KCH; ++kk) {
           if (k0 + kk < kp) {
@@ -728,22 +778,33 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
     __syncthreads();  // final sperm of this sub-panel
     // (5) write the sub-panel back: U rows above, the factored rows, L below
     //     (row pointers again: interchanges moved rows between positions)
+    if (sw == SW && vec) {
 #pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      const int p = c0 + tid + NT * q;
-      if (p < n) {
-        T* wr = el.lrow(p) + cs;
-#pragma unroll
-        for (int j = 0; j < SW; ++j)
-          if (j < sw) wr[j] = x[q][j];
+      for (int q = 0; q < QA; ++q) {
+        const int p = c0 + tid + NT * q;
+        if (p < n) store_row16(el.lrow(p) + cs, x[q]);
       }
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+        if (xrc[q]) store_row16(xrc[q], xc[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        const int p = c0 + tid + NT * q;
+        if (p < n) {
+          T* wr = el.lrow(p) + cs;
+#pragma unroll
+          for (int j = 0; j < SW; ++j)
+            if (j < sw) wr[j] = x[q][j];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QC; ++q)
+        if (xrc[q])
+#pragma unroll
+          for (int j = 0; j < SW; ++j)
+            if (j < sw) xrc[q][j] = xc[q][j];
     }
-#pragma unroll
-    for (int q = 0; q < QC; ++q)
-      if (xrc[q])
-#pragma unroll
-        for (int j = 0; j < SW; ++j)
-          if (j < sw) xrc[q][j] = xc[q][j];
     // the sub-panel rows' own unit-lower L (positions cs .. cs+sw-1 are
     // slot 0 of threads kp .. kp+sw-1) into Lb[:, kp:kp+sw]
     if (tid >= kp && tid < kp + sw) {

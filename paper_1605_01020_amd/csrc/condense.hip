@@ -161,6 +161,26 @@ struct Elem {
   __device__ __attribute__((always_inline)) T* lrow(int row) const {
     return row < n ? LU + (size_t)sperm[row] * n : L21 + (size_t)(row - n) * n;
   }
+  // One column segment of position `row` (SEG 0: columns [0, n), SEG 1:
+  // columns [n, N)), indexed by col - seg_base<SEG>(): the same entries as
+  // st() and in() reach, with the row resolved once for all its columns.
+  template <int SEG>
+  __device__ __attribute__((always_inline)) int seg_base() const { return SEG ? n : 0; }
+  template <int SEG>
+  __device__ __attribute__((always_inline)) T* out_row(int row) const {
+    if constexpr (SEG == 0) return lrow(row);
+    return row < n ? U12 + (size_t)sperm[row] * t : Ke + (size_t)(row - n) * t;
+  }
+  template <int SEG>
+  __device__ __attribute__((always_inline)) const T* in_row(int row) const {
+    if constexpr (sizeof(T) == 4) {
+      return out_row<SEG>(row);  // FP32: inputs were copied into the outputs
+    } else if constexpr (SEG == 0) {
+      return row < n ? A + (size_t)sperm[row] * n : C + (size_t)(row - n) * n;
+    } else {
+      return row < n ? B + (size_t)sperm[row] * t : D + (size_t)(row - n) * t;
+    }
+  }
 };
 
 template <typename T> struct Pair;
@@ -348,11 +368,102 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
 // along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
 // wave 64 x 32).  k-slabs of KC go through two LDS stages; each thread keeps
 // the global loads of the next two slabs in flight in two register buffers.
+// Accumulators initialised with the tile's input values (zero outside
+// rlim x clim).  SEG >= 0: every column of the tile lies in that segment, so
+// each row is resolved once.
+template <typename T, int TM, int TN, int SEG>
+__device__ __attribute__((always_inline)) inline void tile_inputs(const Elem<T>& el, int r0, int rlim, int c0, int clim,
+                                                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+  typedef Tile<T, TM, TN> TL;
+  typedef Mfma<T> MF;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
+#pragma unroll
+  for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + wr0 + 16 * rb + MF::row(lane, v);
+      if constexpr (SEG >= 0) {
+        const T* ip = el.template in_row<SEG>(row);
+        const int base = el.template seg_base<SEG>();
+#pragma unroll
+        for (int cb = 0; cb < TL::CB; ++cb) {
+          const int col = c0 + wc0 + 16 * cb + (lane & 15);
+          acc[rb][cb][v] = (row < rlim && col < clim) ? ip[col - base] : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < TL::CB; ++cb) {
+          const int col = c0 + wc0 + 16 * cb + (lane & 15);
+          acc[rb][cb][v] = (row < rlim && col < clim) ? el.in(row, col) : T(0);
+        }
+      }
+    }
+}
+
+// Store this wave's accumulators inside rlim x clim; SEG as above.
+template <typename T, int TM, int TN, int SEG>
+__device__ __attribute__((always_inline)) inline void tile_store(const Elem<T>& el, int r0, int rlim, int c0, int clim,
+                                                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+  typedef Tile<T, TM, TN> TL;
+  typedef Mfma<T> MF;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
+#pragma unroll
+  for (int rb = 0; rb < TL::RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r0 + wr0 + 16 * rb + MF::row(lane, v);
+      if (row < rlim) {
+        if constexpr (SEG >= 0) {
+          T* op = el.template out_row<SEG>(row);
+          const int base = el.template seg_base<SEG>();
+#pragma unroll
+          for (int cb = 0; cb < TL::CB; ++cb) {
+            const int col = c0 + wc0 + 16 * cb + (lane & 15);
+            if (col < clim) op[col - base] = acc[rb][cb][v];
+          }
+        } else {
+#pragma unroll
+          for (int cb = 0; cb < TL::CB; ++cb) {
+            const int col = c0 + wc0 + 16 * cb + (lane & 15);
+            if (col < clim) el.st(row, col, acc[rb][cb][v]);
+          }
+        }
+      }
+    }
+}
+
+// seg: the column segment every column of the tile lies in (0 or 1), or -1
+// (uniform across the workgroup, so the branch costs nothing per element)
+template <typename T, int TM, int TN>
+__device__ __attribute__((always_inline)) inline void tile_inputs_seg(const Elem<T>& el, int r0, int rlim, int c0, int clim,
+                                                                      typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                                                      int seg) {
+  if (seg == 0) tile_inputs<T, TM, TN, 0>(el, r0, rlim, c0, clim, acc);
+  else if (seg == 1) tile_inputs<T, TM, TN, 1>(el, r0, rlim, c0, clim, acc);
+  else tile_inputs<T, TM, TN, -1>(el, r0, rlim, c0, clim, acc);
+}
+template <typename T, int TM, int TN>
+__device__ __attribute__((always_inline)) inline void tile_store_seg(const Elem<T>& el, int r0, int rlim, int c0, int clim,
+                                                                     typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                                                     int seg) {
+  if (seg == 0) tile_store<T, TM, TN, 0>(el, r0, rlim, c0, clim, acc);
+  else if (seg == 1) tile_store<T, TM, TN, 1>(el, r0, rlim, c0, clim, acc);
+  else tile_store<T, TM, TN, -1>(el, r0, rlim, c0, clim, acc);
+}
+// The column segment of tile columns [j0, jl): 0, 1, or -1 when it straddles
+// n or holds the right-hand-side column.
+__device__ __attribute__((always_inline)) inline int tile_seg(int j0, int jl, int n, int N) {
+  return jl <= n ? 0 : (j0 >= n && jl <= N) ? 1 : -1;
+}
+
 // The slab loop is unrolled by two so that stage and buffer indices are
 // compile-time constants.
 template <typename T, int TM, int TN, int MM = 0, bool HASW = false>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
-                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
+                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                 int seg = -1) {
   typedef Tile<T, TM, TN> TL;
   typedef Mfma<T> MF;
   typedef typename Pair<T>::v P2;
@@ -360,15 +471,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
   const int lane = threadIdx.x & 63;
   if (K <= 0) {
-#pragma unroll
-    for (int rb = 0; rb < TL::RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < TL::CB; ++cb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = r0 + wr0 + 16 * rb + MF::row(lane, v), col = c0 + wc0 + 16 * cb + (lane & 15);
-          acc[rb][cb][v] = (row < rlim && col < clim) ? el.in(row, col) : T(0);
-        }
+    tile_inputs_seg<T, TM, TN>(el, r0, rlim, c0, clim, acc, seg);
     return;
   }
   const int nch = (K + KC - 1) / KC;
@@ -384,15 +487,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   ld.load(0, a0, b0, w0);
   ld.load(1, a1, b1, w1);
   // the tile's input values, read while the first slabs are in flight
-#pragma unroll
-  for (int rb = 0; rb < TL::RB; ++rb)
-#pragma unroll
-    for (int cb = 0; cb < TL::CB; ++cb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + wr0 + 16 * rb + MF::row(lane, v), col = c0 + wc0 + 16 * cb + (lane & 15);
-        acc[rb][cb][v] = (row < rlim && col < clim) ? el.in(row, col) : T(0);
-      }
+  tile_inputs_seg<T, TM, TN>(el, r0, rlim, c0, clim, acc, seg);
   ld.store(0, S0, a0, b0, w0);
   ld.load(2, a0, b0, w0);
   __syncthreads();
@@ -929,10 +1024,8 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     // 1. panel column in Crout order
     for (int r0 = c0; r0 < N; r0 += 256) {
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, 256, 64, MM>(el, r0, N, c0, c1, c0, sg, acc);
-      for_acc<T, 256, 64>(r0, c0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
-        if (row < N && col < c1) el.st(row, col, v);
-      });
+      gemm_tile<T, 256, 64, MM>(el, r0, N, c0, c1, c0, sg, acc, 0);  // columns < c1 <= n
+      tile_store_seg<T, 256, 64>(el, r0, N, c0, c1, acc, 0);
     }
     sync_global();
     // 2. factor the panel, growing L_pp^{-1}
@@ -951,10 +1044,11 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = c1; j0 < NC; j0 += 256) {
       const int jl = min(j0 + 256, NC);
       typename MF::acc_t acc[TB::RB][TB::CB];
+      const int seg = tile_seg(j0, jl, n, N);
       if (jl > N)  // this tile holds the right-hand-side column
         gemm_tile<T, 64, 256, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
       else
-        gemm_tile<T, 64, 256, MM, false>(el, c0, c1, j0, jl, c0, sg, acc);
+        gemm_tile<T, 64, 256, MM, false>(el, c0, c1, j0, jl, c0, sg, acc, seg);
       map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? v : T(0);
       });
@@ -977,9 +1071,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
           for (int cb = 0; cb < TB::CB; ++cb) acc[ib][cb] = nacc[cb];
         }
       }
-      for_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
-        if (row < c1 && col < jl) el.st(row, col, v);
-      });
+      tile_store_seg<T, 64, 256>(el, c0, c1, j0, jl, acc, seg);
     }
     sync_global();
   }
@@ -988,13 +1080,12 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     for (int j0 = n; j0 < NC; j0 += 64) {
       const int jl = min(j0 + 64, NC);
       typename MF::acc_t acc[TA::RB][TA::CB];
+      const int seg = tile_seg(j0, jl, n, N);  // 1, or -1 with the right-hand side
       if (jl > N)
         gemm_tile<T, 256, 64, MM, true>(el, r0, N, j0, jl, n, sg, acc);
       else
-        gemm_tile<T, 256, 64, MM, false>(el, r0, N, j0, jl, n, sg, acc);
-      for_acc<T, 256, 64>(r0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) {
-        if (row < N && col < jl) el.st(row, col, v);
-      });
+        gemm_tile<T, 256, 64, MM, false>(el, r0, N, j0, jl, n, sg, acc, seg);
+      tile_store_seg<T, 256, 64>(el, r0, N, j0, jl, acc, seg);
     }
   }
   for (int i = tid; i < n; i += NT) a.perm[(size_t)e * n + i] = sperm[i];

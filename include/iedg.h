@@ -121,7 +121,10 @@ iedg_status iedg_mesh_query(iedg_mesh mesh, iedg_mesh_info* info, int32_t* order
  *   U12 and entry i of w sit in row perm[i] (the row of A they came from).
  *   L21, Ke and r are indexed by the rows of C.
  * Outputs must not overlap inputs.  A zero or non-finite pivot latches
- * IEDG_ERR_SINGULAR with the element index. */
+ * IEDG_ERR_SINGULAR with the element index.
+ * Limits: n a multiple of 4 and at most 2560, t even and at most 1024
+ * (IEDG_ERR_UNSUPPORTED otherwise); every array 16-byte aligned, as device
+ * allocators return it (IEDG_ERR_INVALID_ARG otherwise). */
 iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local,
                           int32_t n_trace_elem, iedg_prec prec,
                           const double* A, const double* B, const double* C,

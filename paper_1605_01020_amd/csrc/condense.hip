@@ -24,6 +24,7 @@
 //        second MFMA pass on the accumulators (each wave owns whole columns)
 //   4. Schur block: M[n:, n:] = in - L21 U12 (MFMA, K = n)
 #include <climits>
+#include <initializer_list>
 
 #include "common.h"
 
@@ -1249,6 +1250,15 @@ using namespace iedg;
 
 extern "C" void iedg_batch_destroy(iedg_batch b);
 
+// Every array of a condensation starts on a 16-byte boundary: the kernel
+// moves FP32/FP64 data in 8- and 16-byte vectors (with n a multiple of 4 and
+// t even, every element's block then starts aligned too).
+static bool aligned16(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (reinterpret_cast<uintptr_t>(p) & 15) return false;
+  return true;
+}
+
 extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n_local, int32_t n_trace_elem,
                                      iedg_prec prec, const double* A, const double* B, const double* C,
                                      const double* D, const double* F, void* LU, int32_t* perm, void* U12,
@@ -1264,6 +1274,8 @@ extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: n must be a multiple of 4, t even");
   if (n_local > 5 * NT || n_trace_elem > 2 * NT)
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: n=%d t=%d too large", n_local, n_trace_elem);
+  if (!aligned16({A, B, C, D, F, LU, perm, U12, L21, w, Ke, r}))
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "condense: arrays must be 16-byte aligned");
   hipError_t err;
   if (prec == IEDG_F64) {
     CondenseArgs<double> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
@@ -1339,6 +1351,8 @@ extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const 
     if (g.n_elem < 0 || (g.n_elem > 0 && (!g.A || !g.B || !g.C || !g.D || !g.LU || !g.perm || !g.U12 || !g.L21 || !g.Ke)))
       return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d incomplete", s);
     if (g.F && (!g.w || !g.r)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d F without w, r", s);
+    if (!aligned16({g.A, g.B, g.C, g.D, g.F, g.LU, g.perm, g.U12, g.L21, g.w, g.Ke, g.r}))
+      return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d arrays must be 16-byte aligned", s);
     maxE = std::max(maxE, (int)g.n_elem);
     a64.push_back(CondenseArgs<double>{g.n_elem, n_local, n_trace_elem, g.A, g.B, g.C, g.D, g.F, (double*)g.LU,
                                        (double*)g.U12, (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r,

@@ -455,6 +455,12 @@ def test_argument_errors(ctx):
                            None, p(z), None, s0) == -1
     assert L.iedg_condense(ctx.h, 1, 8, 4, 7, p(z), p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
                            None, p(z), None, s0) == -7
+    # an array off a 16-byte boundary (the kernel moves 16-byte vectors)
+    z8 = ctypes.c_void_p(z.data_ptr() + 8)
+    assert L.iedg_condense(ctx.h, 1, 8, 4, F64, p(z), p(z), p(z), p(z), None, z8, p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -1
+    assert L.iedg_condense(ctx.h, 1, 8, 4, F64, z8, p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
+                           None, p(z), None, s0) == -1
     # sub-panel width, GMRES restart and state size
     assert L.iedg_set_leaf_width(ctx.h, F64, 1280, 4) == -1
     m, spec, blocks, G = host_case((1, 1, 1), 1)

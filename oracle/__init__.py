@@ -16,7 +16,8 @@ Galerkin method", section 2.2):
 * left-preconditioned restarted GMRES with iterated classical Gram-Schmidt
   on M^{-1} K dU = M^{-1} R (section 2.2.2, eq. LS1);
 * M = L~ U~, the zero-fill block incomplete LU (BILU(0)) of K under a given
-  row ordering (section 2.2.2);
+  row ordering (section 2.2.2), and the minimum discarded fill ordering the
+  paper applies to it;
 * recovery of the element unknowns dZ_e = A_e^{-1} (F_e - B_e dU_e), which
   the paper leaves implicit ("readily eliminated").
 
@@ -27,6 +28,7 @@ from .mesh import TraceMesh
 from .condense import condense_element, condense_all
 from .assembly import assemble
 from .ordering import natural_order, greedy_colour_order, level_sets
+from .mdf import mdf_order
 from .bilu0 import bilu0, bilu0_apply
 from .gmres import gmres
 from .backsolve import backsolve_element, backsolve_all
@@ -35,7 +37,7 @@ from .solve import newton_step_solve
 
 __all__ = [
     "TraceMesh", "condense_element", "condense_all", "assemble",
-    "natural_order", "greedy_colour_order", "level_sets", "bilu0",
+    "natural_order", "greedy_colour_order", "level_sets", "mdf_order", "bilu0",
     "bilu0_apply", "gmres", "backsolve_element", "backsolve_all",
     "full_residual", "newton_step_solve",
 ]

@@ -1,7 +1,10 @@
 """Assembly of the trace system K dU = R (section 2.2.1, eq. LS).
 
-Parity: pinned through the dense uncondensed solve (tests) and the
-closed-form block count nnzb = N_f + 30 E of a structured hex mesh.
+Parity: pinned through the dense uncondensed solve (tests: the assembled K
+and R equal the Schur complement of the dense system), and the closed-form
+block count nnzb = N_f + 30 E of a structured hex mesh.  ``to_dense`` and
+``matvec`` are pinned with it (the dense comparison goes through
+``to_dense``; GMRES on ``matvec`` reproduces the dense solve).
 
 K is returned as a dict {(f, g): b x b block}; every element adds its 36
 face-pair blocks of K_e.  R = G + sum_e P_e^T r_e.
@@ -32,25 +35,6 @@ def to_dense(tmesh, K):
     for (f, g), blk in K.items():
         M[f * b:(f + 1) * b, g * b:(g + 1) * b] = blk
     return M
-
-
-def to_csr(tmesh, K):
-    import scipy.sparse as sp
-    return sp.csr_matrix(to_dense(tmesh, K)) if tmesh.n_trace <= 6000 else _bsr(tmesh, K)
-
-
-def _bsr(tmesh, K):
-    import scipy.sparse as sp
-    b = tmesh.b
-    keys = sorted(K.keys())
-    indptr = np.zeros(tmesh.n_face + 1, dtype=np.int64)
-    for f, _ in keys:
-        indptr[f + 1] += 1
-    indptr = np.cumsum(indptr)
-    indices = np.array([g for _, g in keys], dtype=np.int64)
-    data = np.stack([K[k] for k in keys])
-    return sp.bsr_matrix((data, indices, indptr),
-                         shape=(tmesh.n_trace, tmesh.n_trace)).tocsr()
 
 
 def matvec(tmesh, K, x):

@@ -5,9 +5,10 @@ independent set of the face graph, every face at level l > 0 has a lower
 neighbour at level l - 1, and the colouring of a structured mesh uses six
 colours (the minimum, since an element's six faces are pairwise coupled).
 
-The paper reorders BILU(0) with minimum discarded fill; this oracle takes the
-ordering as an explicit input and provides two: the natural face order and a
-greedy colouring order.  The greedy colouring visits faces in ascending id
+The paper reorders BILU(0) with minimum discarded fill (oracle/mdf.py, which
+needs the values of K); BILU(0) takes the ordering as an explicit input, and
+this module provides the two orders that depend on the pattern alone: the
+natural face order and a greedy colouring order.  The greedy colouring visits faces in ascending id
 and gives each the smallest colour not held by an already-coloured face that
 shares an element with it; the order lists faces by (colour, face id).
 """

@@ -193,3 +193,56 @@ def test_colour_order_is_valid(dims):
             assert all(lev[g] != lev[f] for g in tm.pattern[f] if g != f)
     lev_c = oracle.level_sets(tm, oracle.greedy_colour_order(tm))
     assert lev_c.max() + 1 == 6
+
+
+def _point_ilu0_product(dense, mask):
+    """Scalar zero-fill ILU(0) (IKJ form, no pivoting) of a dense matrix on
+    the point pattern `mask`, written from the textbook definition; returns
+    the product L U of its unit-lower and upper factors."""
+    a = dense.copy()
+    N = a.shape[0]
+    for i in range(1, N):
+        for k in np.nonzero(mask[i, :i])[0]:
+            a[i, k] /= a[k, k]
+            cols = np.nonzero(mask[i, k + 1:])[0] + k + 1
+            a[i, cols] -= a[i, k] * a[k, cols]
+    L = np.tril(a, -1) + np.eye(N)
+    U = np.triu(a)
+    return L @ U
+
+
+@pytest.mark.parametrize("ordering", ["natural", "colour"])
+def test_point_ilu0_equals_block_ilu0(ordering):
+    """With face-private trace dofs every nonzero block of K is dense, so the
+    scalar ILU(0) on K's point pattern and the b x b block ILU(0) define the
+    same preconditioner M = L U (the block form only groups the arithmetic).
+    Random blocks on the face pattern of a 3x2x2 mesh, b = 3, diagonally
+    dominant pivot blocks (the scalar form does not pivot)."""
+    mesh = StructuredHexMesh(3, 2, 2)
+    b = 3
+    tm = oracle.TraceMesh(mesh.elem_faces(), mesh.n_face, b)
+    rng = np.random.default_rng(11)
+    K = {}
+    for f in range(tm.n_face):
+        for g in tm.pattern[f]:
+            K[(f, g)] = rng.standard_normal((b, b)) * 0.2 + (6.0 * np.eye(b) if f == g else 0)
+    order = oracle.natural_order(tm) if ordering == "natural" else oracle.greedy_colour_order(tm)
+    fac = oracle.bilu0(tm, K, order)
+    # dense copies in the elimination order: point index = position * b + l
+    pos = fac["pos"]
+    N = tm.n_trace
+    dense = np.zeros((N, N))
+    mask = np.zeros((N, N), dtype=bool)
+    for (f, g), blk in K.items():
+        r, c = pos[f] * b, pos[g] * b
+        dense[r:r + b, c:c + b] = blk
+        mask[r:r + b, c:c + b] = True
+    Mp = _point_ilu0_product(dense, mask)
+    Mb = np.zeros((N, N))
+    for (f, g), blk in product_blocks(tm, fac).items():
+        r, c = pos[f] * b, pos[g] * b
+        Mb[r:r + b, c:c + b] = blk
+    assert np.abs(Mp - Mb).max() <= 1e-13 * np.abs(dense).max()
+    # not trivially K: both discard the same fill outside the pattern
+    assert np.abs(Mp - dense)[~mask].max() > 1e-3
+    assert np.abs(Mp - dense)[mask].max() <= 1e-13 * np.abs(dense).max()

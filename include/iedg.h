@@ -28,9 +28,9 @@
  *   immediately (nothing is enqueued).  Conditions detected on the device
  *   (a zero or non-finite pivot) are latched in a device status word and
  *   reported by iedg_sync_status().
- * - The library may allocate device workspace on first use of a size
- *   (GMRES basis, reduction buffers); later calls of the same or smaller
- *   size do not allocate.
+ * - Hot calls do not allocate.  Device memory the library needs beyond the
+ *   caller's arrays is allocated when an object is created (context, mesh,
+ *   GMRES state, batch plan) and freed when it is destroyed.
  * - A context is not thread-safe; use one per host thread.
  */
 #ifndef IEDG_H
@@ -167,10 +167,12 @@ iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch batch, hipStream_
 void iedg_batch_destroy(iedg_batch batch);
 /* Tuning of the condensation kernel: width of the register-resident
  * sub-panels of the panel factorisation (8 or 16 columns) for `prec`
- * (IEDG_F64 or IEDG_F32) and elements with n local dofs.  Process-wide; a
- * width that the register file cannot hold for that case spills to scratch
- * memory (slower, same result).  Untuned: 16 for FP32 with n <= 1536 and
- * t <= 512 and for FP64 with n <= 512 and t <= 512, else 8. */
+ * (IEDG_F64, IEDG_F32 or IEDG_BF16) and elements with n local dofs, kept in
+ * the context (thread-safe).  BF16 without an entry of its own uses the
+ * FP32 entry.  A width that the register file cannot hold for that case
+ * spills to scratch memory (slower, same result).  Untuned: 16 for FP32
+ * with n <= 1536 and t <= 512 and for FP64 with n <= 512 and t <= 512,
+ * else 8. */
 iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int32_t n_local,
                                 int32_t leaf_width);
 
@@ -209,15 +211,35 @@ typedef struct {
   double rel_resid;     /* final ||R - K x|| / ||R|| */
 } iedg_gmres_info;
 
-/* Solves M^{-1} K x = M^{-1} R from x0 = 0 (x is output only).  CGS
- * applied twice per step; Givens rotations; every Krylov quantity FP64.
- * K (and M) blocks in kprec (mprec) storage.  SYNCHRONISES the stream: it
- * reads the residual estimate back after every step.  Returns
- * IEDG_ERR_NOT_CONVERGED (with *info filled) when max_iters is reached. */
-iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,
-                             const void* Kbsr, iedg_prec mprec, const void* Mbsr,
-                             const double* R, double* x, const iedg_gmres_opts* opts,
-                             iedg_gmres_info* info, hipStream_t stream);
+/* GMRES workspace of one mesh: the Krylov basis of up to `steps` vectors,
+ * reduction partials, the Hessenberg matrix and rotations, device scalars,
+ * pinned host slots and two events, all allocated here (steps in [1, 254];
+ * IEDG_ERR_INVALID_ARG otherwise, IEDG_ERR_OOM when the allocation fails).
+ * A state serves one solve or enqueued cycle at a time; it is not shared
+ * between streams. */
+typedef struct iedg_gmres_state_s* iedg_gmres_state;
+iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
+                                    iedg_gmres_state* out);
+void iedg_gmres_state_destroy(iedg_gmres_state st);
+
+/* Solves M^{-1} K x = M^{-1} R from x0 = 0 (x is output only) by restarted
+ * GMRES(opts->restart), restart <= the state's steps (section 2.2.2,
+ * eq. LS1).  CGS applied twice per step; Givens rotations; every Krylov
+ * quantity FP64.  K (and M) blocks in kprec (mprec) storage.  Uses only the
+ * state's workspace (no allocation).  The stopping rule runs on the device:
+ * after it fires, the Arnoldi kernels already queued return at once.  The
+ * host enqueues steps in chunks of four and, while a chunk is queued,
+ * reads the stop flag the previous chunk left (it never waits on the
+ * stream inside a cycle); it waits for the stream once per cycle, for the
+ * true residual that decides acceptance or restart, so the call returns
+ * with the stream synchronised.  Returns IEDG_ERR_NOT_CONVERGED (with *info
+ * filled) when max_iters is reached, IEDG_ERR_NONFINITE for a non-finite
+ * right-hand side or residual. */
+iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st,
+                             iedg_prec kprec, const void* Kbsr, iedg_prec mprec,
+                             const void* Mbsr, const double* R, double* x,
+                             const iedg_gmres_opts* opts, iedg_gmres_info* info,
+                             hipStream_t stream);
 
 /* Capturable GMRES: one cycle of at most `steps` Arnoldi steps from x0 = 0,
  * enqueued with no host synchronisation (it can be captured in a HIP
@@ -228,16 +250,12 @@ iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,
  * completes, iedg_gmres_state_read returns iterations, the true relative
  * residual and whether it met rtol (a cycle is not restarted on the
  * device: the caller may fall back to iedg_gmres_solve). */
-typedef struct iedg_gmres_state_s* iedg_gmres_state;
-iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
-                                    iedg_gmres_state* out);
 iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st,
                                iedg_prec kprec, const void* Kbsr, iedg_prec mprec,
                                const void* Mbsr, const double* R, double* x, double rtol,
                                double inner_factor, hipStream_t stream);
 /* Synchronous read of the state's results (host). */
 iedg_status iedg_gmres_state_read(iedg_context ctx, iedg_gmres_state st, iedg_gmres_info* info);
-void iedg_gmres_state_destroy(iedg_gmres_state st);
 
 /* y = K x (kprec blocks, FP64 vectors); exposed for testing and refinement. */
 iedg_status iedg_spmv(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec,

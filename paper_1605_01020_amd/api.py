@@ -211,9 +211,10 @@ def set_leaf_width(ctx, n_local, leaf_width, prec=F32):
 
 
 class GmresState:
-    """Device-resident GMRES cycle (iedg_gmres_state_*): enqueue() issues no
-    host synchronisation, so it can be captured in a graph; read() returns
-    the outcome after the stream has completed."""
+    """GMRES workspace of one mesh (iedg_gmres_state_*), allocated once.
+    gmres_solve(..., state=) runs restarted GMRES in it; enqueue() runs one
+    device-driven cycle with no host synchronisation (it can be captured in a
+    graph) and read() returns its outcome after the stream has completed."""
 
     def __init__(self, ctx, mesh, steps):
         self.ctx, self.mesh = ctx, mesh
@@ -272,12 +273,23 @@ def factor_ilu0(ctx, mesh, Kbsr, prec=F64, Mbsr=None):
 
 
 def gmres_solve(ctx, mesh, Kbsr, Mbsr, R, restart, rtol, max_iters=10000, inner_factor=0.1,
-                kprec=F64, mprec=F64, precond=True, x=None, raise_on_fail=True):
+                kprec=F64, mprec=F64, precond=True, x=None, raise_on_fail=True, state=None):
+    """GMRES(restart) in the workspace of `state` (a GmresState of this mesh
+    with at least `restart` steps); without one, a state is created for this
+    call and freed after it."""
     x = torch.empty_like(R) if x is None else x
-    opts = GmresOpts(restart, max_iters, rtol, inner_factor, 1 if precond else 0)
-    info = GmresInfo()
-    st = ctx.L.iedg_gmres_solve(ctx.h, mesh.h, kprec, _p(Kbsr), mprec, _p(Mbsr) if precond else None,
-                                _p(R), _p(x), ctypes.byref(opts), ctypes.byref(info), _stream())
+    own = state is None
+    if own:
+        state = GmresState(ctx, mesh, restart)
+    try:
+        opts = GmresOpts(restart, max_iters, rtol, inner_factor, 1 if precond else 0)
+        info = GmresInfo()
+        st = ctx.L.iedg_gmres_solve(ctx.h, mesh.h, state.h, kprec, _p(Kbsr), mprec,
+                                    _p(Mbsr) if precond else None, _p(R), _p(x), ctypes.byref(opts),
+                                    ctypes.byref(info), _stream())
+    finally:
+        if own:
+            state.close()
     res = {"iters": info.iters, "cycles": info.cycles, "converged": bool(info.converged),
            "rel_resid": info.rel_resid, "status": st}
     if st != 0 and (raise_on_fail or st != -3):

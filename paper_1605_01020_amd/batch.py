@@ -197,8 +197,10 @@ class Simulation:
             p = self.prec
             api.condense_rhs(self.ctx, self.fac, self.rF, prec=p, w=self.wc, r=self.rc)
             api.assemble(self.ctx, self.mesh, r=self.rc, G=self.rG, prec=p, R=self.Rc)
-            _, info = api.gmres_solve(self.ctx, self.mesh, self.K, self.M, self.Rc, self.restart, crtol,
-                                      kprec=p, mprec=p, x=self.du)
+            # restarted GMRES in the workspace of the first captured cycle
+            gm = self.gm[0]
+            _, info = api.gmres_solve(self.ctx, self.mesh, self.K, self.M, self.Rc, gm.steps, crtol,
+                                      kprec=p, mprec=p, x=self.du, state=gm)
             api.backsolve_local(self.ctx, self.mesh, self.fac, self.du, prec=p, w=self.wc, z=self.dz)
             api.axpy(self.ctx, 1.0, self.du, self.uhat)
             api.axpy(self.ctx, 1.0, self.dz, self.z)

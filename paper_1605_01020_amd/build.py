@@ -16,7 +16,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-result"]
 
-IEDG_SOURCES = ["context.hip", "condense.hip", "sparse.hip", "krylov.hip", "local.hip"]
+IEDG_SOURCES = ["context.hip", "condense.hip", "condense_f64.hip", "condense_f32.hip", "condense_bf16.hip",
+                "sparse.hip", "krylov.hip", "local.hip"]
 
 
 def _run(cmd):

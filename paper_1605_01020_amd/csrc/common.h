@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -151,16 +152,16 @@ struct iedg_context_s {
   iedg::DeviceStatus* d_status = nullptr;   // device
   iedg::DeviceStatus* h_status = nullptr;   // pinned host mirror
   double* h_scalars = nullptr;              // pinned host readback area
-  // GMRES / reduction workspace, grown on demand
-  void* work = nullptr;
-  size_t work_bytes = 0;
+  // condensation sub-panel widths by (precision, n), set by the autotuner
+  struct LeafChoice { int prec, n, lw; };
+  std::vector<LeafChoice> leaf;
+  std::mutex leaf_mu;
 };
 
 namespace iedg {
 
 iedg_status set_error(iedg_context ctx, iedg_status s, const char* fmt, ...);
 iedg_status hip_check(iedg_context ctx, hipError_t e, const char* what);
-iedg_status ensure_work(iedg_context ctx, size_t bytes);
 
 }  // namespace iedg
 

@@ -25,21 +25,6 @@ iedg_status hip_check(iedg_context ctx, hipError_t e, const char* what) {
   return set_error(ctx, IEDG_ERR_HIP, "%s failed: %s", what, hipGetErrorString(e));
 }
 
-iedg_status ensure_work(iedg_context ctx, size_t bytes) {
-  if (bytes <= ctx->work_bytes) return IEDG_OK;
-  if (ctx->work) {
-    hipDeviceSynchronize();
-    hipFree(ctx->work);
-    ctx->work = nullptr;
-    ctx->work_bytes = 0;
-  }
-  bytes = (bytes + 4095) & ~size_t(4095);
-  hipError_t e = hipMalloc(&ctx->work, bytes);
-  if (e != hipSuccess) return set_error(ctx, IEDG_ERR_OOM, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
-  ctx->work_bytes = bytes;
-  return IEDG_OK;
-}
-
 template <typename T>
 static iedg_status upload(iedg_context ctx, T** dst, const std::vector<T>& src) {
   size_t bytes = std::max<size_t>(1, src.size()) * sizeof(T);
@@ -95,7 +80,6 @@ void iedg_destroy(iedg_context ctx) {
   if (ctx->d_status) hipFree(ctx->d_status);
   if (ctx->h_status) hipHostFree(ctx->h_status);
   if (ctx->h_scalars) hipHostFree(ctx->h_scalars);
-  if (ctx->work) hipFree(ctx->work);
   delete ctx;
 }
 

@@ -278,122 +278,11 @@ extern "C" iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, cons
   return IEDG_OK;
 }
 
-extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_prec kprec, const void* Kbsr,
-                                        iedg_prec mprec, const void* Mbsr, const double* R, double* x,
-                                        const iedg_gmres_opts* opts, iedg_gmres_info* info, hipStream_t stream) {
-  if (!ctx || !mesh || !Kbsr || !R || !x || !opts) return IEDG_ERR_INVALID_ARG;
-  const int m = opts->restart;
-  if (m < 1 || m > MAXV - 2) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: restart %d outside [1, %d]", m, MAXV - 2);
-  if (opts->precond && !Mbsr) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: precond without factors");
-  if (!(opts->rtol > 0.0)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: rtol must be > 0");
-  const int64_t N = mesh->n_trace;
-  const int nb = (int)((N + KCH - 1) / KCH);
-  const int ldp = m + 2;
-  // workspace layout (doubles)
-  const int64_t ldv = (N + 63) & ~int64_t(63);
-  size_t off = 0;
-  auto take = [&](size_t count) { size_t o = off; off += (count + 63) & ~size_t(63); return o; };
-  const size_t oV = take((size_t)(m + 1) * ldv), oT = take(ldv), oP1 = take((size_t)nb * ldp),
-               oP2 = take((size_t)nb * ldp), oP3 = take((size_t)nb), oH = take((size_t)(m + 1) * m),
-               oCS = take(m), oSN = take(m), oG = take(m + 1), oY = take(m), oSC = take(sizeof(GmresScal) / 8);
-  iedg_status st = ensure_work(ctx, off * sizeof(double));
-  if (st != IEDG_OK) return st;
-  double* W = static_cast<double*>(ctx->work);
-  double *V = W + oV, *tmp = W + oT, *P1 = W + oP1, *P2 = W + oP2, *P3 = W + oP3, *H = W + oH, *CS = W + oCS,
-         *SN = W + oSN, *G = W + oG, *Y = W + oY;
-  GmresScal* SC = reinterpret_cast<GmresScal*>(W + oSC);
-  GmresScal* hsc = reinterpret_cast<GmresScal*>(ctx->h_scalars);
-  auto readback = [&]() -> iedg_status {
-    IEDG_HIP(ctx, hipMemcpyAsync(hsc, SC, sizeof(GmresScal), hipMemcpyDeviceToHost, stream));
-    IEDG_HIP(ctx, hipStreamSynchronize(stream));
-    return IEDG_OK;
-  };
-  auto precond = [&](const double* in, double* out) -> iedg_status {
-    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream, nullptr);
-    hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, out, in, N);
-    return IEDG_OK;
-  };
-  // norm of a vector into SC->norm (and SC->inv_scale); optional g init
-  auto vnorm = [&](const double* v, double* ginit) -> iedg_status {
-    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, v, ldv, 0, v, N, P3, 1, 0, nullptr);
-    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, ginit, m + 1);
-    return readback();
-  };
-  iedg_gmres_info inf{0, 0, 0, 0.0};
-  // ||R||
-  if ((st = vnorm(R, nullptr)) != IEDG_OK) return st;
-  const double nR = hsc->norm;
-  if (!std::isfinite(nR)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: right-hand side is not finite");
-  hipLaunchKernelGGL(fill_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, N, 0.0);
-  if (nR == 0.0) {
-    inf.converged = 1;
-    if (info) *info = inf;
-    return IEDG_OK;
-  }
-  // ||M^{-1} R|| sets the inner tolerance
-  if ((st = precond(R, tmp)) != IEDG_OK) return st;
-  if ((st = vnorm(tmp, nullptr)) != IEDG_OK) return st;
-  const double inner_tol = opts->inner_factor * opts->rtol * hsc->norm;
-  double rho = 1.0;
-  bool first = true;
-  while (true) {
-    // true residual r = R - K x (x = 0 on the first cycle)
-    if (first) {
-      hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, tmp, R, N);
-    } else {
-      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream, nullptr)) != IEDG_OK) return st;
-    }
-    if ((st = vnorm(tmp, nullptr)) != IEDG_OK) return st;
-    rho = hsc->norm / nR;
-    first = false;
-    if (!std::isfinite(rho)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: residual is not finite");
-    if (rho <= opts->rtol) { inf.converged = 1; break; }
-    if (inf.iters >= opts->max_iters) break;
-    inf.cycles++;
-    // v0 = M^{-1} r / ||M^{-1} r||,  g = (beta, 0, ...)
-    if ((st = precond(tmp, V)) != IEDG_OK) return st;
-    if ((st = vnorm(V, G)) != IEDG_OK) return st;
-    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, N, SC, nullptr);
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      double* vj = V + (int64_t)j * ldv;
-      double* w = V + (int64_t)(j + 1) * ldv;
-      if ((st = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream, nullptr)) != IEDG_OK) return st;
-      if ((st = precond(tmp, w)) != IEDG_OK) return st;
-      const int nv = j + 1;
-      double* hcol = H + (int64_t)j * (m + 1);
-      // pass 1 dots (+ ||w||^2 before orthogonalisation at index nv)
-      hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv, nullptr);
-      // pass 1 update + pass 2 dots
-      hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, nb, ldp, hcol, 0,
-                         P2, ldp, 1, nullptr);
-      // pass 2 update + ||w||^2
-      hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P2, nb, ldp, hcol, 1,
-                         P3, 1, 0, nullptr);
-      hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, P1, ldp, nv, H, m + 1, j, CS,
-                         SN, G, SC, 0, 0);
-      hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, SC, nullptr);
-      IEDG_LAUNCH_CHECK(ctx, "arnoldi launch");
-      if ((st = readback()) != IEDG_OK) return st;
-      inf.iters++;
-      k = j + 1;
-      const bool breakdown = hsc->hn <= 1e-14 * hsc->wn0;
-      if (!std::isfinite(hsc->est)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: Arnoldi produced non-finite values");
-      if (hsc->est <= inner_tol || breakdown || inf.iters >= opts->max_iters) break;
-    }
-    hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, H, m + 1, G, k, Y, nullptr);
-    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, k, Y, N, nullptr);
-    IEDG_LAUNCH_CHECK(ctx, "gmres update launch");
-  }
-  inf.rel_resid = rho;
-  if (info) *info = inf;
-  if (!inf.converged)
-    return set_error(ctx, IEDG_ERR_NOT_CONVERGED, "gmres: %d iterations, relative residual %.3e > %.3e", inf.iters, rho,
-                     opts->rtol);
-  return IEDG_OK;
-}
-
-// ---- capturable GMRES cycle ------------------------------------------------
+// ---- GMRES workspace (the state) ----------------------------------------------
+// Everything a solve needs beyond its inputs and outputs is allocated when
+// the state is created: the Krylov basis, reduction partials, Hessenberg
+// matrix, rotations, the device scalars, pinned host slots for reading them
+// back and two events.  Solves and enqueues only launch kernels and copy.
 struct iedg_gmres_state_s {
   iedg_mesh mesh = nullptr;
   int steps = 0, nb = 0, ldp = 0;
@@ -401,12 +290,23 @@ struct iedg_gmres_state_s {
   double* buf = nullptr;
   double *V, *tmp, *P1, *P2, *P3, *H, *CS, *SN, *G, *Y;
   GmresScal* SC;
+  GmresScal* h_sc = nullptr;   // pinned: [0] cycle-end readback, [1..2] chunk flags
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
+
+extern "C" void iedg_gmres_state_destroy(iedg_gmres_state st) {
+  if (!st) return;
+  if (st->buf) hipFree(st->buf);
+  if (st->h_sc) hipHostFree(st->h_sc);
+  for (hipEvent_t e : st->ev)
+    if (e) hipEventDestroy(e);
+  delete st;
+}
 
 extern "C" iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
                                                iedg_gmres_state* out) {
   if (!ctx || !mesh || !out || steps < 1 || steps > MAXV - 2)
-    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres_state_create: steps %d", steps);
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres_state_create: steps %d outside [1, %d]", steps, MAXV - 2);
   auto* st = new iedg_gmres_state_s();
   st->mesh = mesh;
   st->steps = steps;
@@ -421,9 +321,12 @@ extern "C" iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh,
                oP2 = take((size_t)st->nb * st->ldp), oP3 = take((size_t)st->nb), oH = take((size_t)(m + 1) * m),
                oCS = take(m), oSN = take(m), oG = take(m + 1), oY = take(m), oSC = take(sizeof(GmresScal) / 8 + 1);
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&st->buf), off * sizeof(double));
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&st->h_sc), 3 * sizeof(GmresScal), hipHostMallocDefault);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&st->ev[i], hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete st;
-    return set_error(ctx, IEDG_ERR_OOM, "gmres_state_create: %zu bytes", off * sizeof(double));
+    iedg_gmres_state_destroy(st);
+    return set_error(ctx, IEDG_ERR_OOM, "gmres_state_create: %zu bytes: %s", off * sizeof(double),
+                     hipGetErrorString(e));
   }
   double* W = st->buf;
   st->V = W + oV; st->tmp = W + oT; st->P1 = W + oP1; st->P2 = W + oP2; st->P3 = W + oP3; st->H = W + oH;
@@ -433,12 +336,148 @@ extern "C" iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh,
   return IEDG_OK;
 }
 
-extern "C" void iedg_gmres_state_destroy(iedg_gmres_state st) {
-  if (!st) return;
-  if (st->buf) hipFree(st->buf);
-  delete st;
+// Arnoldi steps the host enqueues between two looks at the device's stop
+// flag (the look at a chunk happens while the next chunk is already queued).
+constexpr int GMRES_CHUNK = 4;
+
+// Arnoldi step j of a cycle under device control (sc->done set by the
+// stopping rule makes every later kernel of the cycle return at once).
+static iedg_status arnoldi_step(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st, iedg_prec kprec,
+                                const void* Kbsr, iedg_prec mprec, const void* Mbsr, int precond, int j, int steps,
+                                hipStream_t stream) {
+  const int64_t N = st->N, ldv = st->ldv;
+  const int nb = st->nb, ldp = st->ldp, ldh = st->steps + 1;
+  const int* done = &st->SC->done;
+  double* vj = st->V + (int64_t)j * ldv;
+  double* w = st->V + (int64_t)(j + 1) * ldv;
+  iedg_status s;
+  if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, st->tmp, 0, stream, done)) != IEDG_OK) return s;
+  if (precond) {
+    if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, st->tmp, w, stream, done)) != IEDG_OK) return s;
+  } else {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, st->tmp, N);
+  }
+  const int nv = j + 1;
+  double* hcol = st->H + (int64_t)j * ldh;
+  // pass 1 dots (+ ||w||^2 before orthogonalisation at index nv)
+  hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, st->V, ldv, nv, w, N, st->P1, ldp, nv, done);
+  // pass 1 update + pass 2 dots
+  hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, st->V, ldv, nv, w, N, st->P1, nb, ldp,
+                     hcol, 0, st->P2, ldp, 1, done);
+  // pass 2 update + ||w||^2
+  hipLaunchKernelGGL(cgs_update_kernel, dim3(nb), dim3(KTHR), 0, stream, st->V, ldv, nv, w, N, st->P2, nb, ldp,
+                     hcol, 1, st->P3, 1, 0, done);
+  hipLaunchKernelGGL(arnoldi_finish_kernel, dim3(1), dim3(64), 0, stream, st->P3, nb, st->P1, ldp, nv, st->H, ldh,
+                     j, st->CS, st->SN, st->G, st->SC, 1, steps);
+  hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, N, st->SC, done);
+  IEDG_LAUNCH_CHECK(ctx, "arnoldi launch");
+  return IEDG_OK;
 }
 
+__global__ void gmres_cycle_begin_kernel(GmresScal* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  sc->done = 0;
+  sc->k = 0;
+}
+
+extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st, iedg_prec kprec,
+                                        const void* Kbsr, iedg_prec mprec, const void* Mbsr, const double* R,
+                                        double* x, const iedg_gmres_opts* opts, iedg_gmres_info* info,
+                                        hipStream_t stream) {
+  if (!ctx || !mesh || !st || !Kbsr || !R || !x || !opts) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: null argument");
+  if (st->mesh != mesh) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: the state belongs to another mesh");
+  const int m = opts->restart;
+  if (m < 1 || m > st->steps)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: restart %d outside [1, %d] (the state's size)", m, st->steps);
+  if (opts->precond && !Mbsr) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: precond without factors");
+  if (!(opts->rtol > 0.0)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: rtol must be > 0");
+  if (opts->max_iters < 0) return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres: max_iters < 0");
+  const int64_t N = st->N, ldv = st->ldv;
+  const int nb = st->nb, ldh = st->steps + 1;
+  GmresScal* SC = st->SC;
+  double *V = st->V, *tmp = st->tmp, *P3 = st->P3;
+  auto precond = [&](const double* in, double* out) -> iedg_status {
+    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream, nullptr);
+    hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, out, in, N);
+    return IEDG_OK;
+  };
+  auto vnorm = [&](const double* v, double* ginit) {
+    hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, v, ldv, 0, v, N, P3, 1, 0, nullptr);
+    hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, ginit, ldh);
+  };
+  iedg_status s;
+  // x0 = 0; ||R|| and the inner threshold inner_factor * rtol * ||M^{-1} R||, on the device
+  hipLaunchKernelGGL(fill_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, N, 0.0);
+  vnorm(R, nullptr);
+  hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 0, opts->rtol, opts->inner_factor);
+  if ((s = precond(R, tmp)) != IEDG_OK) return s;
+  vnorm(tmp, nullptr);
+  hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 1, opts->rtol, opts->inner_factor);
+  iedg_gmres_info inf{0, 0, 0, 0.0};
+  GmresScal* hsc = st->h_sc;
+  bool first = true;
+  while (true) {
+    // true residual r = R - K x (x = 0 on the first cycle) and rho = ||r|| / ||R||
+    if (first) {
+      hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, tmp, R, N);
+    } else {
+      if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, x, R, tmp, 1, stream, nullptr)) != IEDG_OK) return s;
+    }
+    vnorm(tmp, nullptr);
+    hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 2, opts->rtol, opts->inner_factor);
+    IEDG_LAUNCH_CHECK(ctx, "gmres cycle launch");
+    // the cycle-end readback: the only point where the host waits for the stream
+    IEDG_HIP(ctx, hipMemcpyAsync(&hsc[0], SC, sizeof(GmresScal), hipMemcpyDeviceToHost, stream));
+    IEDG_HIP(ctx, hipStreamSynchronize(stream));
+    if (first) {
+      if (!std::isfinite(hsc[0].nR)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: right-hand side is not finite");
+      if (hsc[0].nR == 0.0) { inf.converged = 1; break; }
+    } else {
+      inf.iters += hsc[0].k;
+    }
+    const double rho = hsc[0].rho;
+    inf.rel_resid = rho;
+    if (!std::isfinite(rho)) return set_error(ctx, IEDG_ERR_NONFINITE, "gmres: residual is not finite");
+    if (hsc[0].converged) { inf.converged = 1; break; }
+    if (inf.iters >= opts->max_iters) break;
+    first = false;
+    inf.cycles++;
+    // v0 = M^{-1} r / ||M^{-1} r||,  g = (beta, 0, ...)
+    hipLaunchKernelGGL(gmres_cycle_begin_kernel, dim3(1), dim3(64), 0, stream, SC);
+    if ((s = precond(tmp, V)) != IEDG_OK) return s;
+    vnorm(V, st->G);
+    hipLaunchKernelGGL(scale_kernel, dim3(grid1(N)), dim3(256), 0, stream, V, N, SC, nullptr);
+    const int steps = std::min(m, opts->max_iters - inf.iters);
+    // Arnoldi steps in chunks: after queueing chunk c the host reads the stop
+    // flag that chunk c-1 left (its copy was queued behind it), so the device
+    // never waits for the host; steps queued after the stop return at once
+    int j = 0, c = 0;
+    bool stop = false;
+    while (j < steps && !stop) {
+      const int j1 = std::min(steps, j + GMRES_CHUNK);
+      for (; j < j1; ++j)
+        if ((s = arnoldi_step(ctx, mesh, st, kprec, Kbsr, mprec, Mbsr, opts->precond, j, steps, stream)) != IEDG_OK)
+          return s;
+      IEDG_HIP(ctx, hipMemcpyAsync(&hsc[1 + (c & 1)], SC, sizeof(GmresScal), hipMemcpyDeviceToHost, stream));
+      IEDG_HIP(ctx, hipEventRecord(st->ev[c & 1], stream));
+      if (c > 0) {
+        IEDG_HIP(ctx, hipEventSynchronize(st->ev[(c - 1) & 1]));
+        stop = hsc[1 + ((c - 1) & 1)].done != 0;
+      }
+      ++c;
+    }
+    hipLaunchKernelGGL(hsolve_kernel, dim3(1), dim3(64), 0, stream, st->H, ldh, st->G, 0, st->Y, SC);
+    hipLaunchKernelGGL(multi_axpy_kernel, dim3(grid1(N)), dim3(256), 0, stream, x, V, ldv, 0, st->Y, N, SC);
+    IEDG_LAUNCH_CHECK(ctx, "gmres update launch");
+  }
+  if (info) *info = inf;
+  if (!inf.converged)
+    return set_error(ctx, IEDG_ERR_NOT_CONVERGED, "gmres: %d iterations, relative residual %.3e > %.3e", inf.iters,
+                     inf.rel_resid, opts->rtol);
+  return IEDG_OK;
+}
+
+// ---- capturable GMRES cycle ------------------------------------------------
 extern "C" iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st, iedg_prec kprec,
                                           const void* Kbsr, iedg_prec mprec, const void* Mbsr, const double* R,
                                           double* x, double rtol, double inner_factor, hipStream_t stream) {

@@ -54,6 +54,8 @@ class NewtonStepSolver:
         self.K = None
         self.M = None
         self.prec = None
+        # the GMRES workspace, allocated once for every solve of this mesh
+        self.gm = api.GmresState(ctx, mesh, restart)
 
     # -- factorisation (the part that depends on the matrices only) --------
     def factor(self, A, B, C, D, F=None, prec=F64, timer=None):
@@ -71,7 +73,7 @@ class NewtonStepSolver:
 
     def _trace_solve(self, R, rtol, max_iters=10000):
         return api.gmres_solve(self.ctx, self.mesh, self.K, self.M, R, self.restart, rtol, max_iters=max_iters,
-                               kprec=self.prec, mprec=self.prec)
+                               kprec=self.prec, mprec=self.prec, state=self.gm)
 
     # -- FP64 form ----------------------------------------------------------
     def solve_fp64(self, A, B, C, D, F, G, rtol, timer=None):

@@ -42,8 +42,12 @@ def _clean_status(request):
 
 
 SEED = SEED_BASE + 3
+# degrees 1 to 4: the batched condensation instantiations for n <= 512,
+# n <= 1536 (p = 3, b = 80) and n <= 2560 (p = 4, b = 125), and the sweep
+# lane groups of every face size, all run here
 CASES = [MeshCase(0, (2, 2, 1), 1), MeshCase(1, (2, 1, 1), 2), MeshCase(2, (1, 1, 2), 1),
-         MeshCase(3, (1, 2, 1), 2), MeshCase(4, (1, 1, 1), 1)]
+         MeshCase(3, (1, 2, 1), 2), MeshCase(4, (1, 1, 1), 1), MeshCase(5, (2, 1, 1), 3),
+         MeshCase(6, (1, 2, 1), 4)]
 
 
 def _trace_system(ctx, dims, p, prec=0):
@@ -56,10 +60,11 @@ def _trace_system(ctx, dims, p, prec=0):
     return mesh, K, M, R
 
 
+@pytest.mark.parametrize("dims,p", [((2, 2, 2), 1), ((2, 2, 1), 3), ((2, 1, 1), 4)])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_gmres_enqueue_equals_host_cycle(ctx, prec):
-    _say(f"gmres_enqueue vs gmres_solve prec={prec}")
-    mesh, K, M, R = _trace_system(ctx, (2, 2, 2), 1, prec)
+def test_gmres_enqueue_equals_host_cycle(ctx, prec, dims, p):
+    _say(f"gmres_enqueue vs gmres_solve prec={prec} dims={dims} p={p}")
+    mesh, K, M, R = _trace_system(ctx, dims, p, prec)
     x_h, info_h = api.gmres_solve(ctx, mesh, K, M, R, restart=50, rtol=1e-10, kprec=prec, mprec=prec)
     assert info_h["cycles"] == 1 and info_h["converged"]
     st = api.GmresState(ctx, mesh, 50)
@@ -161,7 +166,9 @@ def test_run_batch_groups_under_budget(ctx):
     from paper_1605_01020_amd.batch import run_batch, Simulation
     _say("run_batch with a small memory budget")
     wl = Workload("small_batch", SEED, CASES, restart=100, rtol=1e-8)
-    budget = max(Simulation.footprint(c) for c in CASES) * 1.5
+    # the largest (p = 4) mesh and a fifth of it: not every mesh fits beside it
+    budget = max(Simulation.footprint(c) for c in CASES) * 1.2
+    assert budget < sum(Simulation.footprint(c) for c in CASES)
     out = run_batch(ctx, wl, budget_bytes=budget, replays=2)
     assert out["groups"] >= 2
     assert [r.mesh_id for r in out["results"]] == [c.mesh_id for c in CASES]

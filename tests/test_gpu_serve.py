@@ -35,7 +35,8 @@ def ctx():
 
 SEED = SEED_BASE + 4
 CASES = [MeshCase(0, (2, 2, 1), 1), MeshCase(1, (2, 1, 1), 2), MeshCase(2, (1, 1, 2), 1),
-         MeshCase(3, (1, 2, 1), 2), MeshCase(4, (1, 1, 1), 1), MeshCase(5, (2, 2, 2), 1)]
+         MeshCase(3, (1, 2, 1), 2), MeshCase(4, (1, 1, 1), 1), MeshCase(5, (2, 2, 2), 1),
+         MeshCase(6, (2, 1, 1), 3), MeshCase(7, (1, 2, 1), 4)]
 
 
 def _serve(ctx, requests, n_slots, budget):
@@ -56,7 +57,9 @@ def test_serving_mix_invariance(ctx):
     alone, st_alone = _serve(ctx, [r for r in poisson_requests(SEED, 24, 100.0, len(CASES))], 1, big)
     assert st_alone["evictions"] == 0
     _say("serving mixed (4 slots, budget forcing evictions)")
-    tight = 2.2 * max(Simulation.footprint(c) for c in CASES)
+    # room for the largest simulation and a fifth of it: admitting the p = 4
+    # simulation evicts the others, and the p = 3 one cannot stay beside it
+    tight = 1.2 * max(Simulation.footprint(c) for c in CASES)
     mixed, st_mix = _serve(ctx, reqs, 4, tight)
     assert st_mix["evictions"] > 0 and st_mix["misses"] > st_alone["misses"]
     assert set(alone) == set(mixed) and len(alone) == 24
@@ -74,9 +77,10 @@ def test_serving_result_matches_oracle(ctx):
     from paper_1605_01020_amd.serve import Request
     from paper_1605_01020_amd.batch import Simulation
     big = 10 * sum(Simulation.footprint(c) for c in CASES)
-    reqs = [Request(0, 1, 3, 0.0), Request(1, 5, 2, 0.0), Request(2, 1, 4, 0.0)]
+    reqs = [Request(0, 1, 3, 0.0), Request(1, 5, 2, 0.0), Request(2, 1, 4, 0.0), Request(3, 6, 1, 0.0),
+            Request(4, 7, 2, 0.0)]
     got, st = _serve(ctx, reqs, 2, big)
-    assert st["hits"] == 1 and st["misses"] == 2
+    assert st["hits"] == 1 and st["misses"] == 4
     for (sid, rhs), r in got.items():
         c = CASES[sid]
         _say(f"oracle for sim {sid} rhs {rhs}")

@@ -286,6 +286,23 @@ iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int32_t n_local
                                double* rF, double* rG, double* sums,
                                hipStream_t stream);
 
+/* iedg_residual_full without any library-owned device memory, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results
+ * (bitwise) as iedg_residual_full; its scratch (q [E][t] and 2E + 2 N_f
+ * partial sums) lives in a static device array of 16 MiB (2^21 FP64 values)
+ * that each GPU holds from library load to process end; the call allocates
+ * nothing and needs E t + 2 E + 2 N_f <= 2^21 (IEDG_ERR_UNSUPPORTED
+ * otherwise).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams, not ordered) race and must not be
+ * issued. */
+iedg_status iedg_residual_full_noalloc(iedg_context ctx, iedg_mesh mesh, int32_t n_local,
+                                       const double* A, const double* B, const double* C,
+                                       const double* D, const double* F, const double* G,
+                                       const double* z, const double* uhat,
+                                       double* rF, double* rG, double* sums,
+                                       hipStream_t stream);
+
 /* y += alpha * x over n FP64 values (refinement updates). */
 iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, const double* x,
                       double* y, hipStream_t stream);

@@ -64,6 +64,7 @@ SIGNATURES = {
     "iedg_ilu0_apply": (c_int32, [P, P, c_int32, P, P, P, P]),
     "iedg_backsolve_local": (c_int32, [P, P, c_int32, c_int32, P, P, P, P, P, P, P]),
     "iedg_residual_full": (c_int32, [P, P, c_int32, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "iedg_residual_full_noalloc": (c_int32, [P, P, c_int32, P, P, P, P, P, P, P, P, P, P, P, P]),
     "iedg_axpy": (c_int32, [P, c_int64, c_double, P, P, P]),
 }
 

@@ -162,6 +162,9 @@ namespace iedg {
 
 iedg_status set_error(iedg_context ctx, iedg_status s, const char* fmt, ...);
 iedg_status hip_check(iedg_context ctx, hipError_t e, const char* what);
+// Looks up this context's device address of the allocation-free residual's
+// static scratch (once per device; the device must be current).
+iedg_status residual_scratch_init(iedg_context ctx);
 
 }  // namespace iedg
 

@@ -70,6 +70,10 @@ iedg_status iedg_create(iedg_context* out, int device) {
     iedg_destroy(ctx);
     return IEDG_ERR_HIP;
   }
+  if (residual_scratch_init(ctx) != IEDG_OK) {
+    iedg_destroy(ctx);
+    return IEDG_ERR_HIP;
+  }
   *out = ctx;
   return IEDG_OK;
 }

@@ -1,5 +1,7 @@
 // Element-local kernels on gfx950: recovery of the element unknowns
 // (section 2.2.1) and the FP64 residual of the uncondensed Newton system.
+#include <mutex>
+
 #include "common.h"
 #include "mesh.h"
 
@@ -198,15 +200,16 @@ extern "C" iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, in
   return IEDG_OK;
 }
 
-extern "C" iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int32_t n_local, const double* A,
-                                          const double* B, const double* C, const double* D, const double* F,
-                                          const double* G, const double* z, const double* uhat, double* rF,
-                                          double* rG, double* sums, hipStream_t stream) {
-  if (!ctx || !mesh || !A || !B || !C || !D || !F || !G || !z || !uhat || !rF || !rG || !sums || n_local <= 0)
-    return IEDG_ERR_INVALID_ARG;
-  const int n = n_local, t = mesh->t, b = mesh->b, E = mesh->n_elem, NF = mesh->n_face;
-  // mesh-owned scratch: q [E][t], partials 2E + 2NF
-  double* q = mesh->d_rwork;
+namespace iedg {
+
+// Both residual entry points: `work` holds q [E][t] and the partial sums
+// (2E + 2 n_face values); every entry is written before it is read.
+static iedg_status residual_launch(iedg_context ctx, iedg_mesh mesh, int n, const double* A, const double* B,
+                                   const double* C, const double* D, const double* F, const double* G,
+                                   const double* z, const double* uhat, double* rF, double* rG, double* sums,
+                                   double* work, hipStream_t stream) {
+  const int t = mesh->t, b = mesh->b, E = mesh->n_elem, NF = mesh->n_face;
+  double* q = work;
   double* prf = q + (size_t)E * t;
   double* pf = prf + E;
   double* prg = pf + E;
@@ -221,4 +224,68 @@ extern "C" iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int3
                      (int64_t)NF, sums);
   IEDG_LAUNCH_CHECK(ctx, "residual launch");
   return IEDG_OK;
+}
+
+static size_t residual_work_values(iedg_mesh mesh) {
+  return (size_t)mesh->n_elem * mesh->t + 2 * (size_t)mesh->n_elem + 2 * (size_t)mesh->n_face;
+}
+
+// ---- the allocation-free residual ---------------------------------------
+// File-scope device scratch of the allocation-free entry point.  In host
+// code `residual_scratch` names a host-side stand-in, not device memory: the
+// device address of each GPU's copy is looked up once per device (from
+// iedg_create, with that device current) and only that address is used.
+constexpr size_t kResidualScratchValues = size_t(2) << 20;   // 16 MiB of FP64
+static __device__ __align__(256) double residual_scratch[kResidualScratchValues];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+iedg_status residual_scratch_init(iedg_context ctx) {
+  const int dev = ctx->device;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(ctx, IEDG_ERR_UNSUPPORTED, "device %d >= %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return IEDG_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(residual_scratch));
+  if (e != hipSuccess || !p) return hip_check(ctx, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+  g_scratch_ptr[dev] = static_cast<double*>(p);
+  return IEDG_OK;
+}
+
+}  // namespace iedg
+
+using namespace iedg;
+
+extern "C" iedg_status iedg_residual_full(iedg_context ctx, iedg_mesh mesh, int32_t n_local, const double* A,
+                                          const double* B, const double* C, const double* D, const double* F,
+                                          const double* G, const double* z, const double* uhat, double* rF,
+                                          double* rG, double* sums, hipStream_t stream) {
+  if (!ctx || !mesh || !A || !B || !C || !D || !F || !G || !z || !uhat || !rF || !rG || !sums || n_local <= 0)
+    return IEDG_ERR_INVALID_ARG;
+  // mesh-owned scratch, allocated with the mesh
+  return residual_launch(ctx, mesh, n_local, A, B, C, D, F, G, z, uhat, rF, rG, sums, mesh->d_rwork, stream);
+}
+
+extern "C" iedg_status iedg_residual_full_noalloc(iedg_context ctx, iedg_mesh mesh, int32_t n_local,
+                                                  const double* A, const double* B, const double* C,
+                                                  const double* D, const double* F, const double* G,
+                                                  const double* z, const double* uhat, double* rF, double* rG,
+                                                  double* sums, hipStream_t stream) {
+  if (!ctx || !mesh || !A || !B || !C || !D || !F || !G || !z || !uhat || !rF || !rG || !sums || n_local <= 0)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "residual_full_noalloc: null argument or n <= 0");
+  const size_t need = residual_work_values(mesh);
+  if (need > kResidualScratchValues)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED,
+                     "residual_full_noalloc: needs %zu scratch values (E t + 2 E + 2 n_face), the static "
+                     "scratch holds %zu", need, kResidualScratchValues);
+  double* work = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) work = g_scratch_ptr[ctx->device];
+  }
+  if (!work) return set_error(ctx, IEDG_ERR_HIP, "residual_full_noalloc: scratch address of device %d unknown",
+                              ctx->device);
+  return residual_launch(ctx, mesh, n_local, A, B, C, D, F, G, z, uhat, rF, rG, sums, work, stream);
 }

@@ -84,7 +84,8 @@ iedg_status iedg_sync_status(iedg_context ctx, hipStream_t stream, int64_t* bad_
  * ordering: 0 = greedy colouring (faces visited by ascending id, each takes
  *   the smallest colour unused by an already coloured face sharing an
  *   element; rows listed by (colour, face id)); 1 = natural face order;
- *   2 = the permutation given in `order` (host [n_face]).
+ *   2 = the permutation given in `order` (host [n_face]), e.g. the minimum
+ *   discarded fill order from iedg_mdf_order.
  * BSR layout: block row i (0 <= i < n_face) is face order[i]; its blocks
  * occupy slots row_ptr[i] .. row_ptr[i+1]-1, sorted by the position of their
  * column face in the ordering (so lower blocks, the diagonal, then upper
@@ -194,6 +195,22 @@ iedg_status iedg_assemble(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
  * block latches IEDG_ERR_SINGULAR with the block row. */
 iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
                              const void* Kbsr, void* Mbsr, hipStream_t stream);
+
+/* Minimum discarded fill ordering of the block rows of K (section 2.2.2,
+ * after Persson and Peraire): greedy elimination on the zero-fill pattern;
+ * the weight of a row is the squared Frobenius norm of the fill its
+ * elimination would drop (blocks A_ik A_kk^{-1} A_kj of pairs (i, j) of live
+ * rows coupled to k but not to each other), taken on the matrix as updated
+ * by the earlier eliminations (updates kept on the pattern, as BILU(0)
+ * makes them); each step eliminates the live row of least weight, ties to
+ * the smaller face id.  All in FP64 on the device.  Kbsr: K in the mesh's
+ * BSR layout, `prec` storage.  order (host [n_face]) receives the faces in
+ * elimination order, to be passed to iedg_mesh_create with ordering 2.
+ * A set-up call: it allocates FP64 working arrays (about nnzb + 11 n_face
+ * blocks of b x b), synchronises `stream` and frees them before returning.
+ * A singular pivot block latches IEDG_ERR_SINGULAR (iedg_sync_status). */
+iedg_status iedg_mdf_order(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
+                           const void* Kbsr, int32_t* order, hipStream_t stream);
 
 /* ---- a4: GMRES (section 2.2.2, eq. LS1) ------------------------------- */
 typedef struct {

@@ -54,6 +54,7 @@ SIGNATURES = {
     "iedg_condense_rhs": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P, P, P]),
     "iedg_assemble": (c_int32, [P, P, c_int32, P, P, P, P, P, P]),
     "iedg_factor_ilu0": (c_int32, [P, P, c_int32, P, P, P]),
+    "iedg_mdf_order": (c_int32, [P, P, c_int32, P, P, P]),
     "iedg_gmres_solve": (c_int32, [P, P, P, c_int32, P, c_int32, P, P, P, ctypes.POINTER(GmresOpts),
                                    ctypes.POINTER(GmresInfo), P]),
     "iedg_gmres_state_create": (c_int32, [P, P, c_int32, ctypes.POINTER(c_void_p)]),

@@ -272,6 +272,15 @@ def factor_ilu0(ctx, mesh, Kbsr, prec=F64, Mbsr=None):
     return Mbsr
 
 
+def mdf_order(ctx, mesh, Kbsr, prec=F64):
+    """Minimum discarded fill order of the faces (iedg_mdf_order), host int32
+    array; pass it to Mesh(..., ordering="given", order=...)."""
+    _check_dev(Kbsr)
+    order = np.empty(mesh.n_face, np.int32)
+    ctx.check(ctx.L.iedg_mdf_order(ctx.h, mesh.h, prec, _p(Kbsr), order.ctypes.data_as(ctypes.c_void_p), _stream()))
+    return order
+
+
 def gmres_solve(ctx, mesh, Kbsr, Mbsr, R, restart, rtol, max_iters=10000, inner_factor=0.1,
                 kprec=F64, mprec=F64, precond=True, x=None, raise_on_fail=True, state=None):
     """GMRES(restart) in the workspace of `state` (a GmresState of this mesh

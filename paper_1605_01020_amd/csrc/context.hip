@@ -262,6 +262,7 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
   iedg_status st = IEDG_OK;
   if (st == IEDG_OK) st = upload(ctx, &m->d_elem_faces, ef);
   if (st == IEDG_OK) st = upload(ctx, &m->d_row_face, m->order);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_pos, m->pos);
   if (st == IEDG_OK) st = upload(ctx, &m->d_row_ptr, m->row_ptr);
   if (st == IEDG_OK) st = upload(ctx, &m->d_col_face, m->col_face);
   if (st == IEDG_OK) st = upload(ctx, &m->d_diag_slot, diag_slot);
@@ -287,7 +288,7 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
 
 void iedg_mesh_destroy(iedg_mesh m) {
   if (!m) return;
-  int32_t* ptrs[] = {m->d_elem_faces, m->d_row_face, m->d_row_ptr, m->d_col_face,
+  int32_t* ptrs[] = {m->d_elem_faces, m->d_row_face, m->d_pos, m->d_row_ptr, m->d_col_face,
                      m->d_diag_slot, m->d_level_rows, m->d_asm_src, m->d_face_src,
                      m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd};
   for (int32_t* p : ptrs)

@@ -21,6 +21,7 @@ struct iedg_mesh_s {
   // device copies
   int32_t* d_elem_faces = nullptr;  // [E][6]
   int32_t* d_row_face = nullptr;    // [n_face]
+  int32_t* d_pos = nullptr;         // [n_face]: face -> row
   int32_t* d_row_ptr = nullptr;     // [n_face + 1]
   int32_t* d_col_face = nullptr;    // [nnzb]
   int32_t* d_diag_slot = nullptr;   // [n_face]

@@ -18,6 +18,8 @@ Galerkin method", section 2.2):
 * M = L~ U~, the zero-fill block incomplete LU (BILU(0)) of K under a given
   row ordering (section 2.2.2), and the minimum discarded fill ordering the
   paper applies to it;
+* the restricted additive Schwarz preconditioner with delta-level overlap
+  and BILU(0) subdomain solves (section 2.2.2), for N > 1 subdomains;
 * recovery of the element unknowns dZ_e = A_e^{-1} (F_e - B_e dU_e), which
   the paper leaves implicit ("readily eliminated").
 
@@ -29,6 +31,7 @@ from .condense import condense_element, condense_all
 from .assembly import assemble
 from .ordering import natural_order, greedy_colour_order, level_sets
 from .mdf import mdf_order
+from .ras import ras_setup, ras_apply, overlap
 from .bilu0 import bilu0, bilu0_apply
 from .gmres import gmres
 from .backsolve import backsolve_element, backsolve_all
@@ -37,7 +40,7 @@ from .solve import newton_step_solve
 
 __all__ = [
     "TraceMesh", "condense_element", "condense_all", "assemble",
-    "natural_order", "greedy_colour_order", "level_sets", "mdf_order", "bilu0",
+    "natural_order", "greedy_colour_order", "level_sets", "mdf_order", "ras_setup", "ras_apply", "overlap", "bilu0",
     "bilu0_apply", "gmres", "backsolve_element", "backsolve_all",
     "full_residual", "newton_step_solve",
 ]

@@ -18,8 +18,10 @@ import scipy.linalg as sla
 
 
 def bilu0(tmesh, K, order):
-    pos = np.empty(tmesh.n_face, dtype=np.int64)
-    pos[np.asarray(order)] = np.arange(tmesh.n_face)
+    """`order` lists the block rows to factor (all faces, or the faces of a
+    subdomain whose pattern `tmesh` restricts to them)."""
+    pos = np.full(tmesh.n_face, -1, dtype=np.int64)
+    pos[np.asarray(order)] = np.arange(len(order))
     L, U = {}, {}
     Uinv = {}
     for i in order:

@@ -61,5 +61,22 @@ class StructuredHexMesh:
         d[f], idx[f] = 2, k.ravel()
         return d, idx
 
+    def face_slabs(self, n_sub):
+        """Partition of the faces into n_sub subdomains (input data for the
+        restricted additive Schwarz preconditioner, in place of a graph
+        partitioner): elements go to n_sub slabs of equal width along x
+        (slab of element (i, j, k) = i * n_sub // nx), and a face to the slab
+        of the lowest-numbered element it bounds.  Returns int32 [n_face]."""
+        if not 1 <= n_sub <= self.nx:
+            raise ValueError(f"n_sub must be in [1, {self.nx}]")
+        ef = self.elem_faces()
+        slab_of_elem = (np.arange(self.n_elem) // (self.ny * self.nz)) * n_sub // self.nx
+        part = np.full(self.n_face, -1, dtype=np.int32)
+        for e in range(self.n_elem):          # ascending: the first element wins
+            for f in ef[e]:
+                if part[f] < 0:
+                    part[f] = slab_of_elem[e]
+        return part
+
     def __repr__(self):
         return f"StructuredHexMesh({self.nx}x{self.ny}x{self.nz})"

@@ -1,7 +1,12 @@
 """Parity at the full 16x16x8, p=3 size in the launch configuration the
 benchmark times: sampled element outputs against the oracle computed one by
-one from host-generated inputs, and the uncondensed residual checked on
-sampled element rows and face rows on the host."""
+one from host-generated inputs, the uncondensed residual checked on sampled
+element rows and face rows on the host, and the FP64, FP32-mixed and
+BF16-mixed solutions against stored samples of the streamed FP64 oracle
+solve (tests/golden/subdomain_16x16x8_p3_rhs0.json, written by
+tests/golden/make_subdomain_samples.py from oracle/ and synth/ only)."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -46,6 +51,31 @@ def full1():
 
 
 SAMPLE = [0, 777, 2047]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "subdomain_16x16x8_p3_rhs0.json")
+
+
+def _golden_errors(u, z):
+    """Relative errors of a GPU solution against the oracle samples: uhat on
+    the 512 sampled entries, z on the three stored elements, and the norms."""
+    g = json.load(open(GOLDEN))
+    idx = np.array(g["uhat_index"])
+    uh = u.cpu().numpy()
+    eu = rel(uh[idx], np.array(g["uhat_value"]))
+    ez = max(rel(z[int(e)].cpu().numpy(), np.array(v)) for e, v in g["z_elements"].items())
+    enu = abs(np.linalg.norm(uh) - g["uhat_norm"]) / g["uhat_norm"]
+    enz = abs(float(torch.linalg.norm(z).item()) - g["z_norm"]) / g["z_norm"]
+    return eu, ez, enu, enz
+
+
+def test_fullsize_fp64_matches_oracle_samples(full1):
+    wl, spec, hm, ctx, mesh, d, G, solver, z, u, info = full1
+    g = json.load(open(GOLDEN))
+    assert g["seed"] == wl.seed and tuple(g["dims"]) == (hm.nx, hm.ny, hm.nz) and g["rhs"] == 0
+    eu, ez, enu, enz = _golden_errors(u, z)
+    _say(f"fp64 vs oracle samples: uhat {eu:.2e} z {ez:.2e} |uhat| {enu:.2e} |z| {enz:.2e} "
+         f"(iters {info['iters']}, oracle {g['gmres_iters']})")
+    # rtol 1e-10 on K with kappa(K) of about 4.4
+    assert max(eu, ez, enu, enz) <= 5e-10
 
 
 def test_fullsize_condense_sampled(full1):
@@ -87,16 +117,23 @@ def test_fullsize_fp64_residual_sampled(full1):
     assert np.linalg.norm(rg) <= wl.rtol * scale
 
 
-def test_fullsize_mixed_refinement(full1):
-    from paper_1605_01020_amd import F32
+@pytest.mark.parametrize("form", ["f32", "bf16"])
+def test_fullsize_mixed_refinement(full1, form):
+    from paper_1605_01020_amd import F32, BF16
     from paper_1605_01020_amd.solver import NewtonStepSolver
     wl, spec, hm, ctx, mesh, d, G, solver, z, u, info = full1
     s2 = NewtonStepSolver(ctx, mesh, spec.n, restart=wl.restart)
-    _say("config 1 mixed fp32 solve")
-    z2, u2, info2 = s2.solve_mixed(d["A"], d["B"], d["C"], d["D"], d["F"], G, tol=1e-8, prec=F32)
+    _say(f"config 1 mixed {form} solve")
+    z2, u2, info2 = s2.solve_mixed(d["A"], d["B"], d["C"], d["D"], d["F"], G, tol=1e-8,
+                                   prec=F32 if form == "f32" else BF16)
     ctx.sync_status()
     assert info2["converged_full"], info2["rho_hist"]
     eu = rel(u2.cpu().numpy(), u.cpu().numpy())
     ez = rel(z2.cpu().numpy(), z.cpu().numpy())
-    _say(f"mixed vs fp64: uhat {eu:.2e} z {ez:.2e} rho {info2['rho_hist']} iters {info2['iters']}")
+    gu, gz, gnu, gnz = _golden_errors(u2, z2)
+    _say(f"mixed {form} vs fp64 gpu: uhat {eu:.2e} z {ez:.2e}; vs oracle samples: uhat {gu:.2e} z {gz:.2e} "
+         f"|uhat| {gnu:.2e} |z| {gnz:.2e}; rho {info2['rho_hist']} iters {info2['iters']}")
     assert eu <= 1e-7 and ez <= 1e-7
+    assert max(gu, gz, gnu, gnz) <= 1e-7
+    del s2
+    torch.cuda.empty_cache()

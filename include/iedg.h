@@ -212,6 +212,36 @@ iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
 iedg_status iedg_mdf_order(iedg_context ctx, iedg_mesh mesh, iedg_prec prec,
                            const void* Kbsr, int32_t* order, hipStream_t stream);
 
+/* ---- restricted additive Schwarz (section 2.2.2, RAS equation) -------- */
+/* M^{-1} = sum_i R_i^0 BILU(0)(K_i)^{-1} R_i^delta over n_sub subdomains,
+ * emulated on one GPU.  part (host [n_face]): subdomain of each face (the
+ * non-overlapping S_i^0, every subdomain non-empty); S_i^delta adds `delta`
+ * layers of faces coupled in K (delta = 0: block Jacobi).  K_i = K on
+ * S_i^delta is factored by BILU(0) in the mesh's elimination order
+ * restricted to S_i^delta; R_i^0 keeps only the faces of S_i^0 (restricted
+ * prolongation: each face takes its own subdomain's value).  All subdomain
+ * systems form one block-sparse local system (rows = (subdomain, face)
+ * pairs) whose factors Mloc hold nnzb (from iedg_ras_query) blocks of b x b
+ * in the factor precision.  Creation allocates the local pattern, maps and
+ * two local vectors; factor and apply only launch.  IEDG_ERR_INVALID_ARG for
+ * a bad partition. */
+typedef struct iedg_ras_s* iedg_ras;
+typedef struct {
+  int64_t n_sub, delta, n_local_rows, nnzb, n_levels;
+} iedg_ras_info;
+iedg_status iedg_ras_create(iedg_context ctx, iedg_mesh mesh, int32_t n_sub, const int32_t* part,
+                            int32_t delta, iedg_ras* out);
+void iedg_ras_destroy(iedg_ras ras);
+iedg_status iedg_ras_query(iedg_ras ras, iedg_ras_info* info);
+/* Mloc = the BILU(0) factors of every K_i, from K (the mesh's BSR layout,
+ * `prec` storage); same factor layout and singular-pivot reporting as
+ * iedg_factor_ilu0. */
+iedg_status iedg_ras_factor(iedg_context ctx, iedg_ras ras, iedg_prec prec, const void* Kbsr,
+                            void* Mloc, hipStream_t stream);
+/* y = M^{-1} x (global FP64 vectors [N_t]; y must not alias x). */
+iedg_status iedg_ras_apply(iedg_context ctx, iedg_ras ras, iedg_prec prec, const void* Mloc,
+                           const double* x, double* y, hipStream_t stream);
+
 /* ---- a4: GMRES (section 2.2.2, eq. LS1) ------------------------------- */
 typedef struct {
   int32_t restart;      /* m, Krylov vectors per cycle (>= 1) */
@@ -238,6 +268,11 @@ typedef struct iedg_gmres_state_s* iedg_gmres_state;
 iedg_status iedg_gmres_state_create(iedg_context ctx, iedg_mesh mesh, int32_t steps,
                                     iedg_gmres_state* out);
 void iedg_gmres_state_destroy(iedg_gmres_state st);
+
+/* Makes later solves and enqueued cycles of `st` precondition with the RAS
+ * `ras` (built on the same mesh): Mbsr is then its factors Mloc.  NULL
+ * restores BILU(0) of the whole mesh. */
+iedg_status iedg_gmres_state_set_ras(iedg_context ctx, iedg_gmres_state st, iedg_ras ras);
 
 /* Solves M^{-1} K x = M^{-1} R from x0 = 0 (x is output only) by restarted
  * GMRES(opts->restart), restart <= the state's steps (section 2.2.2,

@@ -29,6 +29,11 @@ class GmresInfo(ctypes.Structure):
                 ("rel_resid", c_double)]
 
 
+class RasInfo(ctypes.Structure):
+    _fields_ = [("n_sub", c_int64), ("delta", c_int64), ("n_local_rows", c_int64), ("nnzb", c_int64),
+                ("n_levels", c_int64)]
+
+
 class CondenseSegment(ctypes.Structure):
     _fields_ = [("n_elem", c_int32), ("A", P), ("B", P), ("C", P), ("D", P), ("F", P),
                 ("LU", P), ("perm", P), ("U12", P), ("L21", P), ("w", P), ("Ke", P), ("r", P)]
@@ -55,6 +60,12 @@ SIGNATURES = {
     "iedg_assemble": (c_int32, [P, P, c_int32, P, P, P, P, P, P]),
     "iedg_factor_ilu0": (c_int32, [P, P, c_int32, P, P, P]),
     "iedg_mdf_order": (c_int32, [P, P, c_int32, P, P, P]),
+    "iedg_ras_create": (c_int32, [P, P, c_int32, P, c_int32, ctypes.POINTER(c_void_p)]),
+    "iedg_ras_destroy": (None, [P]),
+    "iedg_ras_query": (c_int32, [P, ctypes.POINTER(RasInfo)]),
+    "iedg_ras_factor": (c_int32, [P, P, c_int32, P, P, P]),
+    "iedg_ras_apply": (c_int32, [P, P, c_int32, P, P, P, P]),
+    "iedg_gmres_state_set_ras": (c_int32, [P, P, P]),
     "iedg_gmres_solve": (c_int32, [P, P, P, c_int32, P, c_int32, P, P, P, ctypes.POINTER(GmresOpts),
                                    ctypes.POINTER(GmresInfo), P]),
     "iedg_gmres_state_create": (c_int32, [P, P, c_int32, ctypes.POINTER(c_void_p)]),

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import F64, F32, BF16, CondenseSegment, GmresOpts, GmresInfo, MeshInfo
+from ._lib import F64, F32, BF16, CondenseSegment, GmresOpts, GmresInfo, MeshInfo, RasInfo
 
 PREC_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.float32}
 
@@ -228,6 +228,12 @@ class GmresState:
                                                      _p(Mbsr), _p(R), _p(x), float(rtol), float(inner_factor),
                                                      _stream()))
 
+    def set_ras(self, ras):
+        """Precondition with the RAS `ras` (its factors are then the M
+        argument); None restores BILU(0) of the mesh."""
+        self.ctx.check(self.ctx.L.iedg_gmres_state_set_ras(self.ctx.h, self.h, None if ras is None else ras.h))
+        self._ras = ras
+
     def read(self):
         info = GmresInfo()
         self.ctx.check(self.ctx.L.iedg_gmres_state_read(self.ctx.h, self.h, ctypes.byref(info)))
@@ -270,6 +276,47 @@ def factor_ilu0(ctx, mesh, Kbsr, prec=F64, Mbsr=None):
     Mbsr = torch.empty_like(Kbsr) if Mbsr is None else Mbsr
     ctx.check(ctx.L.iedg_factor_ilu0(ctx.h, mesh.h, prec, _p(Kbsr), _p(Mbsr), _stream()))
     return Mbsr
+
+
+class Ras:
+    """Restricted additive Schwarz preconditioner over a face partition
+    (iedg_ras_*): part[f] = subdomain of face f, `delta` overlap layers."""
+
+    def __init__(self, ctx, mesh, part, delta):
+        self.ctx, self.mesh = ctx, mesh
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        n_sub = int(part.max()) + 1
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.iedg_ras_create(ctx.h, mesh.h, n_sub, part.ctypes.data_as(ctypes.c_void_p), int(delta),
+                                        ctypes.byref(h)))
+        self.h = h
+        info = RasInfo()
+        ctx.check(ctx.L.iedg_ras_query(h, ctypes.byref(info)))
+        self.n_sub, self.delta = info.n_sub, info.delta
+        self.n_local_rows, self.nnzb, self.n_levels = info.n_local_rows, info.nnzb, info.n_levels
+
+    def factor(self, Kbsr, prec=F64, Mloc=None):
+        _check_dev(Kbsr)
+        if Mloc is None:
+            Mloc = torch.empty((self.nnzb, self.mesh.b, self.mesh.b), dtype=PREC_DTYPE[prec], device=Kbsr.device)
+        self.ctx.check(self.ctx.L.iedg_ras_factor(self.ctx.h, self.h, prec, _p(Kbsr), _p(Mloc), _stream()))
+        return Mloc
+
+    def apply(self, Mloc, x, prec=F64, y=None):
+        y = torch.empty_like(x) if y is None else y
+        self.ctx.check(self.ctx.L.iedg_ras_apply(self.ctx.h, self.h, prec, _p(Mloc), _p(x), _p(y), _stream()))
+        return y
+
+    def close(self):
+        if self.h:
+            self.ctx.L.iedg_ras_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mdf_order(ctx, mesh, Kbsr, prec=F64):

@@ -33,6 +33,87 @@ static iedg_status upload(iedg_context ctx, T** dst, const std::vector<T>& src) 
   return IEDG_OK;
 }
 
+// BSR pattern, level sets and BILU(0) schedule of a block system whose rows
+// are "faces" 0 .. n_face-1 with coupling lists adj[f] (including f), in
+// the elimination order m->order; uploads the pattern arrays.
+iedg_status build_pattern(iedg_context ctx, iedg_mesh_s* m, const std::vector<std::vector<int>>& adj) {
+  const int NF = m->n_face;
+  m->pos.resize(NF);
+  for (int i = 0; i < NF; ++i) m->pos[m->order[i]] = i;
+  // BSR pattern in position order
+  m->row_ptr.assign(NF + 1, 0);
+  std::vector<int32_t>& diag_slot = m->diag_slot;
+  diag_slot.assign(NF, -1);
+  for (int i = 0; i < NF; ++i) {
+    int f = m->order[i];
+    std::vector<int> cols = adj[f];
+    std::sort(cols.begin(), cols.end(), [&](int x, int y) { return m->pos[x] < m->pos[y]; });
+    m->row_ptr[i + 1] = m->row_ptr[i] + (int)cols.size();
+    for (int g : cols) {
+      if (g == f) diag_slot[i] = (int32_t)m->col_face.size();
+      m->col_face.push_back(g);
+    }
+  }
+  m->nnzb = (int64_t)m->col_face.size();
+  auto slot_of = [&](int i, int g) -> int {
+    for (int s = m->row_ptr[i]; s < m->row_ptr[i + 1]; ++s)
+      if (m->col_face[s] == g) return s;
+    return -1;
+  };
+  // level sets of the lower-triangular dependency graph
+  std::vector<int> level(NF, 0);
+  int nlev = 0;
+  for (int i = 0; i < NF; ++i) {
+    int lv = 0;
+    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) lv = std::max(lv, level[m->pos[m->col_face[s]]] + 1);
+    level[i] = lv;
+    nlev = std::max(nlev, lv + 1);
+  }
+  m->n_levels = nlev;
+  m->level_ptr.assign(nlev + 1, 0);
+  for (int i = 0; i < NF; ++i) m->level_ptr[level[i] + 1]++;
+  for (int l = 0; l < nlev; ++l) m->level_ptr[l + 1] += m->level_ptr[l];
+  m->level_rows.resize(NF);
+  {
+    std::vector<int> fill(m->level_ptr.begin(), m->level_ptr.end() - 1);
+    for (int i = 0; i < NF; ++i) m->level_rows[fill[level[i]]++] = i;
+  }
+  // BILU(0) schedule: for row i, lower slots (i,k) in elimination order; for
+  // each, the updates A_ij -= L_ik U_kj over j later than k coupled to both
+  std::vector<int32_t> lptr(NF + 1, 0), lslots, uptr(1, 0), upd;
+  for (int i = 0; i < NF; ++i) {
+    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) {
+      int k = m->pos[m->col_face[s]];
+      lslots.push_back(s);
+      lslots.push_back(diag_slot[k]);
+      for (int s2 = diag_slot[k] + 1; s2 < m->row_ptr[k + 1]; ++s2) {
+        int j = m->col_face[s2];
+        int sij = slot_of(i, j);
+        if (sij >= 0) {
+          upd.push_back(s2);
+          upd.push_back(sij);
+        }
+      }
+      uptr.push_back((int32_t)(upd.size() / 2));
+    }
+    lptr[i + 1] = (int32_t)(lslots.size() / 2);
+  }
+  m->n_lslots = (int64_t)lslots.size() / 2;
+  m->n_updates = (int64_t)upd.size() / 2;
+  iedg_status st = IEDG_OK;
+  if (st == IEDG_OK) st = upload(ctx, &m->d_row_face, m->order);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_pos, m->pos);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_row_ptr, m->row_ptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_col_face, m->col_face);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_diag_slot, diag_slot);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_level_rows, m->level_rows);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_lptr, lptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_l, lslots);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_uptr, uptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_upd, upd);
+  return st;
+}
+
 }  // namespace iedg
 
 using namespace iedg;
@@ -179,27 +260,11 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
     delete m;
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: unknown ordering %d", ordering);
   }
-  m->pos.resize(NF);
-  for (int i = 0; i < NF; ++i) m->pos[m->order[i]] = i;
-  // BSR pattern in position order
-  m->row_ptr.assign(NF + 1, 0);
-  std::vector<int32_t> diag_slot(NF);
-  for (int i = 0; i < NF; ++i) {
-    int f = m->order[i];
-    std::vector<int> cols = adj[f];
-    std::sort(cols.begin(), cols.end(), [&](int x, int y) { return m->pos[x] < m->pos[y]; });
-    m->row_ptr[i + 1] = m->row_ptr[i] + (int)cols.size();
-    for (int g : cols) {
-      if (g == f) diag_slot[i] = (int32_t)m->col_face.size();
-      m->col_face.push_back(g);
-    }
+  iedg_status st = build_pattern(ctx, m, adj);
+  if (st != IEDG_OK) {
+    iedg_mesh_destroy(m);
+    return st;
   }
-  m->nnzb = (int64_t)m->col_face.size();
-  auto slot_of = [&](int i, int g) -> int {
-    for (int s = m->row_ptr[i]; s < m->row_ptr[i + 1]; ++s)
-      if (m->col_face[s] == g) return s;
-    return -1;
-  };
   // assembly gather map: block (f, g) receives Ke_e[a][c] for every element e
   // holding f at local face a and g at local face c (ascending e)
   std::vector<int32_t> asm_src(2 * m->nnzb, -1);
@@ -218,61 +283,10 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
   for (int f = 0; f < NF; ++f)
     for (size_t k = 0; k < face_elems[f].size(); ++k)
       face_src[2 * f + k] = face_elems[f][k].first * 6 + face_elems[f][k].second;
-  // level sets of the lower-triangular dependency graph
-  std::vector<int> level(NF, 0);
-  int nlev = 0;
-  for (int i = 0; i < NF; ++i) {
-    int lv = 0;
-    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) lv = std::max(lv, level[m->pos[m->col_face[s]]] + 1);
-    level[i] = lv;
-    nlev = std::max(nlev, lv + 1);
-  }
-  m->n_levels = nlev;
-  m->level_ptr.assign(nlev + 1, 0);
-  for (int i = 0; i < NF; ++i) m->level_ptr[level[i] + 1]++;
-  for (int l = 0; l < nlev; ++l) m->level_ptr[l + 1] += m->level_ptr[l];
-  m->level_rows.resize(NF);
-  {
-    std::vector<int> fill(m->level_ptr.begin(), m->level_ptr.end() - 1);
-    for (int i = 0; i < NF; ++i) m->level_rows[fill[level[i]]++] = i;
-  }
-  // BILU(0) schedule: for row i, lower slots (i,k) in elimination order; for
-  // each, the updates A_ij -= L_ik U_kj over j later than k coupled to both
-  std::vector<int32_t> lptr(NF + 1, 0), lslots, uptr(1, 0), upd;
-  for (int i = 0; i < NF; ++i) {
-    for (int s = m->row_ptr[i]; s < diag_slot[i]; ++s) {
-      int k = m->pos[m->col_face[s]];
-      lslots.push_back(s);
-      lslots.push_back(diag_slot[k]);
-      for (int s2 = diag_slot[k] + 1; s2 < m->row_ptr[k + 1]; ++s2) {
-        int j = m->col_face[s2];
-        int sij = slot_of(i, j);
-        if (sij >= 0) {
-          upd.push_back(s2);
-          upd.push_back(sij);
-        }
-      }
-      uptr.push_back((int32_t)(upd.size() / 2));
-    }
-    lptr[i + 1] = (int32_t)(lslots.size() / 2);
-  }
-  m->n_lslots = (int64_t)lslots.size() / 2;
-  m->n_updates = (int64_t)upd.size() / 2;
   std::vector<int32_t> ef(elem_faces, elem_faces + 6 * (size_t)E);
-  iedg_status st = IEDG_OK;
   if (st == IEDG_OK) st = upload(ctx, &m->d_elem_faces, ef);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_row_face, m->order);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_pos, m->pos);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_row_ptr, m->row_ptr);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_col_face, m->col_face);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_diag_slot, diag_slot);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_level_rows, m->level_rows);
   if (st == IEDG_OK) st = upload(ctx, &m->d_asm_src, asm_src);
   if (st == IEDG_OK) st = upload(ctx, &m->d_face_src, face_src);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_lptr, lptr);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_l, lslots);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_uptr, uptr);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_ilu_upd, upd);
   if (st == IEDG_OK) {
     const size_t rw = (size_t)E * m->t + 2 * (size_t)E + 2 * (size_t)NF;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->d_rwork), rw * sizeof(double));

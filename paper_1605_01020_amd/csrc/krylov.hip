@@ -14,6 +14,8 @@ iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const vo
                         const double* rhs, double* y, int mode, hipStream_t stream, const int* skip);
 iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
                               double* y, hipStream_t stream, const int* skip);
+iedg_status ras_apply_launch(iedg_context ctx, iedg_ras ras, iedg_prec mprec, const void* Mloc, const double* x,
+                             double* y, hipStream_t stream, const int* skip);
 
 constexpr int KTHR = 256;
 constexpr int KPER = 8;                 // values per thread per chunk
@@ -292,7 +294,23 @@ struct iedg_gmres_state_s {
   GmresScal* SC;
   GmresScal* h_sc = nullptr;   // pinned: [0] cycle-end readback, [1..2] chunk flags
   hipEvent_t ev[2] = {nullptr, nullptr};
+  iedg_ras ras = nullptr;      // preconditioner: RAS when set, else BILU(0) of the mesh
 };
+
+// M^{-1} x with the state's preconditioner.
+static iedg_status apply_precond(iedg_context ctx, iedg_mesh mesh, iedg_gmres_state st, iedg_prec mprec,
+                                 const void* M, const double* x, double* y, hipStream_t stream, const int* skip) {
+  if (st->ras) return ras_apply_launch(ctx, st->ras, mprec, M, x, y, stream, skip);
+  return ilu0_apply_launch(ctx, mesh, mprec, M, x, y, stream, skip);
+}
+
+extern "C" iedg_status iedg_gmres_state_set_ras(iedg_context ctx, iedg_gmres_state st, iedg_ras ras) {
+  if (!ctx || !st) return IEDG_ERR_INVALID_ARG;
+  if (ras && ras_mesh(ras) != st->mesh)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "gmres_state_set_ras: the RAS belongs to another mesh");
+  st->ras = ras;
+  return IEDG_OK;
+}
 
 extern "C" void iedg_gmres_state_destroy(iedg_gmres_state st) {
   if (!st) return;
@@ -353,7 +371,7 @@ static iedg_status arnoldi_step(iedg_context ctx, iedg_mesh mesh, iedg_gmres_sta
   iedg_status s;
   if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, st->tmp, 0, stream, done)) != IEDG_OK) return s;
   if (precond) {
-    if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, st->tmp, w, stream, done)) != IEDG_OK) return s;
+    if ((s = apply_precond(ctx, mesh, st, mprec, Mbsr, st->tmp, w, stream, done)) != IEDG_OK) return s;
   } else {
     hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, w, st->tmp, N);
   }
@@ -397,7 +415,7 @@ extern "C" iedg_status iedg_gmres_solve(iedg_context ctx, iedg_mesh mesh, iedg_g
   GmresScal* SC = st->SC;
   double *V = st->V, *tmp = st->tmp, *P3 = st->P3;
   auto precond = [&](const double* in, double* out) -> iedg_status {
-    if (opts->precond) return ilu0_apply_launch(ctx, mesh, mprec, Mbsr, in, out, stream, nullptr);
+    if (opts->precond) return apply_precond(ctx, mesh, st, mprec, Mbsr, in, out, stream, nullptr);
     hipLaunchKernelGGL(copy_kernel, dim3(grid1(N)), dim3(256), 0, stream, out, in, N);
     return IEDG_OK;
   };
@@ -495,7 +513,7 @@ extern "C" iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg
   hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, nullptr, m + 1);
   hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 0, rtol, inner_factor);
   // v0 = M^{-1} R / ||M^{-1} R||, g = (beta, 0, ...)
-  if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, R, tmp, stream, done)) != IEDG_OK) return s;
+  if ((s = apply_precond(ctx, mesh, st, mprec, Mbsr, R, tmp, stream, done)) != IEDG_OK) return s;
   hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, tmp, ldv, 0, tmp, N, P3, 1, 0, done);
   hipLaunchKernelGGL(norm_finish_kernel, dim3(1), dim3(64), 0, stream, P3, nb, 1, 0, SC, st->G, m + 1);
   hipLaunchKernelGGL(gmres_dev_set_kernel, dim3(1), dim3(64), 0, stream, SC, 1, rtol, inner_factor);
@@ -504,7 +522,7 @@ extern "C" iedg_status iedg_gmres_enqueue(iedg_context ctx, iedg_mesh mesh, iedg
     double* vj = V + (int64_t)j * ldv;
     double* w = V + (int64_t)(j + 1) * ldv;
     if ((s = spmv_launch(ctx, mesh, kprec, Kbsr, vj, nullptr, tmp, 0, stream, done)) != IEDG_OK) return s;
-    if ((s = ilu0_apply_launch(ctx, mesh, mprec, Mbsr, tmp, w, stream, done)) != IEDG_OK) return s;
+    if ((s = apply_precond(ctx, mesh, st, mprec, Mbsr, tmp, w, stream, done)) != IEDG_OK) return s;
     const int nv = j + 1;
     double* hcol = H + (int64_t)j * (m + 1);
     hipLaunchKernelGGL(dots_kernel, dim3(nb), dim3(KTHR), 0, stream, V, ldv, nv, w, N, P1, ldp, nv, done);

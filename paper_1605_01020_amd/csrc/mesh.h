@@ -17,6 +17,7 @@ struct iedg_mesh_s {
   std::vector<int32_t> level_rows;  // rows grouped by level, ascending within a level
   std::vector<int32_t> row_ptr;     // [n_face + 1]
   std::vector<int32_t> col_face;    // [nnzb]
+  std::vector<int32_t> diag_slot;   // [n_face]
 
   // device copies
   int32_t* d_elem_faces = nullptr;  // [E][6]
@@ -37,3 +38,12 @@ struct iedg_mesh_s {
   // owned by the mesh so that residual launches never allocate
   double* d_rwork = nullptr;
 };
+
+namespace iedg {
+// Pattern, level sets and BILU(0) schedule of rows 0 .. m->n_face-1 with
+// coupling lists adj (each including the row itself), in the order
+// m->order; uploads the pattern arrays (context.hip).
+iedg_status build_pattern(iedg_context ctx, iedg_mesh_s* m, const std::vector<std::vector<int>>& adj);
+// The global mesh a RAS preconditioner was built on (ras.hip).
+iedg_mesh ras_mesh(iedg_ras r);
+}  // namespace iedg

@@ -36,6 +36,13 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 
 
+# the sources of the FP32 condensation kernel (HBM counters are reported only
+# while these are unchanged since the counters were taken)
+CONDENSE_SOURCES = ["paper_1605_01020_amd/csrc/condense_kernel.h", "paper_1605_01020_amd/csrc/condense.h",
+                    "paper_1605_01020_amd/csrc/condense_f32.hip", "paper_1605_01020_amd/csrc/common.h",
+                    "paper_1605_01020_amd/tuning.json"]
+
+
 def condense_flops(n, t):
     # LU of A, U12 = L^{-1} P B, L21 = C U^{-1}, Schur product L21 U12
     return (2.0 / 3.0) * n ** 3 + 2.0 * n * n * t + 2.0 * n * t * t
@@ -76,7 +83,16 @@ def cpu_baseline(seed, restart):
     per_face = med[1] / sub.n_face
     step_s = per_elem * full.n_elem + per_face * full.n_face
     work = sum(sum(r) for r in runs)
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 1.0 / step_s, "unit": "Newton-step solves/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": cpu_model, "nproc": os.cpu_count(), "blas_threads": int(threads),
             "sample": (f"oracle FP64 solve of a 4x2x2 p=3 mesh with the same distributions ({sub.n_elem} "
                        f"elements, {sub.n_face} faces, {info['iters']} GMRES iterations), median of 3; element "
                        f"phases scaled by {full.n_elem}/{sub.n_elem}, trace phases by {full.n_face}/{sub.n_face}; "
@@ -100,7 +116,7 @@ def measured_traffic(kernel_sources, profile):
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("source-sha256 (condense.hip + tuning.json)") != h.hexdigest():
+    if fields.get("source-sha256") != h.hexdigest():
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -112,12 +128,30 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def batch_form(ctx, prec, args, replays=2):
+    """The 24-mesh uneven batch in one precision form (F32: FP32 condensation
+    and trace system with FP64 refinement; F64: plain FP64).  Time: mean of
+    the graph replays per memory group (generation excluded)."""
+    import torch
+    from paper_1605_01020_amd.batch import run_batch
+    from synth.matrices import workload
+    wl = workload(3)
+    out = run_batch(ctx, wl, budget_bytes=args.budget_gb * 1e9, prec=prec, replays=replays, log=_log)
+    res = out["results"]
+    E = sum(m.mesh.n_elem for m in wl.meshes)
+    torch.cuda.empty_cache()
+    return {"solves_per_s": len(res) / out["seconds"], "seconds": out["seconds"],
+            "seconds_min_replay": out["seconds_min"], "seconds_median_replay": out["seconds_median"],
+            "elements_per_s": E / out["seconds"], "groups": out["groups"],
+            "max_rho_full": max(r.rho_hist[-1] for r in res), "all_converged": all(r.converged for r in res),
+            "eager_steps": sum(r.eager_steps for r in res)}
+
+
 def bench_batch(args):
     """Batched form over the 24-mesh uneven batch; a step is one pass over
     every mesh (generation of the inputs excluded from the timed region)."""
     import torch
-    from paper_1605_01020_amd import api, F32
-    from paper_1605_01020_amd.batch import run_batch
+    from paper_1605_01020_amd import api, F32, F64
     from paper_1605_01020_amd.autotune import apply_tuning
     from synth.matrices import workload
     wl = workload(3)
@@ -126,22 +160,19 @@ def bench_batch(args):
     apply_tuning(ctx)
     E = sum(m.mesh.n_elem for m in wl.meshes)
     flops = sum(condense_flops(m.spec.n, m.spec.t) * m.mesh.n_elem for m in wl.meshes)
-    out = run_batch(ctx, wl, budget_bytes=args.budget_gb * 1e9, prec=F32, replays=max(1, args.steps), log=_log)
-    res = out["results"]
-    secs = out["seconds"]
+    forms = {"f32": batch_form(ctx, F32, args, max(1, args.steps)), "f64": batch_form(ctx, F64, args, max(1, args.steps))}
+    r = forms["f32"]
     line = {
         "metric": "Newton-step solves/s at relative residual 1e-8, batched form (24 uneven meshes)",
-        "value": len(res) / secs, "unit": "Newton-step solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": 1, "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic (seeded Philox element blocks generated in HBM per memory group)",
+        "value": r["solves_per_s"], "unit": "Newton-step solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": r["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (seeded Philox element blocks generated in HBM per memory group)",
         "config": {"workload": f"24 meshes from {{4^3, 6^3, 8x8x4, 12x12x6}} x p in {{2,3,4}}, E={E}, "
                                f"condensation {flops:.3e} flop, GMRES(100)+BILU(0), tol 1e-8",
-                   "groups": out["groups"], "budget_gb": args.budget_gb},
-        "elements_per_s": E / secs,
-        "condense_tflops_equiv": flops / secs / 1e12,
-        "max_rho_full": max(r.rho_hist[-1] for r in res),
-        "all_converged": all(r.converged for r in res),
-        "eager_steps": sum(r.eager_steps for r in res),
+                   "budget_gb": args.budget_gb},
+        "forms": forms,
+        "speedup_mixed_vs_fp64": forms["f32"]["solves_per_s"] / forms["f64"]["solves_per_s"],
+        "condense_tflops_equiv": flops / r["seconds"] / 1e12,
     }
     print(json.dumps(line), flush=True)
 
@@ -183,6 +214,141 @@ def bench_serving(args):
     print(json.dumps(line), flush=True)
 
 
+def _ms(fn, reps=1):
+    """Average milliseconds of fn() on the current stream (HIP events)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extra_fp64_tight(ctx, mesh, n, mats, Fs, Gs, restart, rtol=1e-10, steps=3):
+    """The plain FP64 form at the workload's own tolerance (1e-10 on K)."""
+    import torch
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    A, B, C, D = mats
+    solver = NewtonStepSolver(ctx, mesh, n, restart=restart)
+    solver.solve_fp64(A, B, C, D, Fs[0], Gs[0], rtol=rtol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for k in range(steps):
+        _, _, info = solver.solve_fp64(A, B, C, D, Fs[k % len(Fs)], Gs[k % len(Gs)], rtol=rtol)
+        iters.append(info["iters"])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"solves_per_s": 1e3 / ms, "ms_per_step": ms, "rtol": rtol, "gmres_iters": iters}
+
+
+def extra_rhs_solves(ctx, mesh, n, mats, Fs, Gs, restart):
+    """Right-hand-side-only solves with retained factors: every right-hand
+    side of the sequence after one factorisation (FP64 at 1e-10 and 1e-8;
+    mixed FP32 with FP64 refinement at 1e-8)."""
+    import torch
+    from paper_1605_01020_amd import api, F64, F32
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    A, B, C, D = mats
+    out = {}
+    for name, prec, tol in (("fp64_1e-10", F64, 1e-10), ("fp64_1e-8", F64, 1e-8), ("mixed_f32_1e-8", F32, 1e-8)):
+        solver = NewtonStepSolver(ctx, mesh, n, restart=restart)
+        solver.factor(A, B, C, D, None, prec=prec)
+        torch.cuda.synchronize()
+        iters, rhos = [], []
+        t0 = time.perf_counter()
+        for F, G in zip(Fs, Gs):
+            if prec == F64:
+                z, u, info = solver.solve_rhs_fp64(F, G, tol)
+            else:
+                z, u, info = solver.solve_rhs_mixed(A, B, C, D, F, G, tol=tol)
+                rhos.append(info["rho_full"])
+            iters.append(info["iters"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / len(Fs)
+        out[name] = {"rhs_solves_per_s": 1e3 / ms, "ms_per_rhs": ms, "gmres_iters": iters}
+        if rhos:
+            out[name]["max_rho_full"] = max(rhos)
+        del solver
+        torch.cuda.empty_cache()
+    return out
+
+
+def extra_orderings(ctx, hmesh, spec, mats, F, G, restart, rtol=1e-10):
+    """BILU(0) under the natural, colour and minimum discarded fill orders
+    (FP64): levels, factorisation and application time, GMRES iterations."""
+    import torch
+    from paper_1605_01020_amd import api, F64
+    A, B, C, D = mats
+    fac = api.condense(ctx, A, B, C, D, F, prec=F64)
+    out = {}
+    meshes = {}
+    for name in ("natural", "colour", "mdf"):
+        if name == "mdf":
+            base = meshes["colour"]
+            Kc, _ = api.assemble(ctx, base, Ke=fac["Ke"], prec=F64)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            order = api.mdf_order(ctx, base, Kc, prec=F64)
+            t_mdf = time.perf_counter() - t0
+            del Kc
+            mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b, ordering="given", order=order)
+        else:
+            mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b, ordering=name)
+        meshes[name] = mesh
+        K, R = api.assemble(ctx, mesh, Ke=fac["Ke"], r=fac["r"], G=G, prec=F64)
+        M = torch.empty_like(K)
+        api.factor_ilu0(ctx, mesh, K, prec=F64, Mbsr=M)
+        t_fac = _ms(lambda: api.factor_ilu0(ctx, mesh, K, prec=F64, Mbsr=M), 2)
+        y = torch.empty_like(R)
+        t_app = _ms(lambda: api.ilu0_apply(ctx, mesh, M, R, y=y), 5)
+        st = api.GmresState(ctx, mesh, restart)
+        _, info = api.gmres_solve(ctx, mesh, K, M, R, restart, rtol, state=st)
+        t_gm = _ms(lambda: api.gmres_solve(ctx, mesh, K, M, R, restart, rtol, state=st))
+        out[name] = {"levels": mesh.n_levels, "factor_ms": t_fac, "apply_ms": t_app, "gmres_iters": info["iters"],
+                     "gmres_ms": t_gm}
+        if name == "mdf":
+            out[name]["ordering_s"] = t_mdf
+        st.close()
+        del K, M, R, y
+        torch.cuda.empty_cache()
+    return out
+
+
+def extra_ras(ctx, hmesh, spec, mats, F, G, restart, rtol=1e-10, subs=(1, 2, 4, 8), deltas=(0, 1)):
+    """The paper's restricted additive Schwarz preconditioner with N slab
+    subdomains on one GPU (FP64): GMRES iterations against N and delta."""
+    import torch
+    from paper_1605_01020_amd import api, F64
+    A, B, C, D = mats
+    fac = api.condense(ctx, A, B, C, D, F, prec=F64)
+    mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b)
+    K, R = api.assemble(ctx, mesh, Ke=fac["Ke"], r=fac["r"], G=G, prec=F64)
+    del fac
+    out = {}
+    st = api.GmresState(ctx, mesh, restart)
+    for n_sub in subs:
+        for delta in deltas:
+            ras = api.Ras(ctx, mesh, hmesh.face_slabs(n_sub), delta)
+            Ml = ras.factor(K, prec=F64)
+            t_fac = _ms(lambda: ras.factor(K, prec=F64, Mloc=Ml))
+            y = torch.empty_like(R)
+            t_app = _ms(lambda: ras.apply(Ml, R, y=y), 5)
+            st.set_ras(ras)
+            _, info = api.gmres_solve(ctx, mesh, K, Ml, R, restart, rtol, state=st, raise_on_fail=False)
+            out[f"N{n_sub}_delta{delta}"] = {"gmres_iters": info["iters"], "converged": info["converged"],
+                                             "local_rows": ras.n_local_rows, "levels": ras.n_levels,
+                                             "factor_ms": t_fac, "apply_ms": t_app}
+            st.set_ras(None)
+            ras.close()
+            del Ml, y
+            torch.cuda.empty_cache()
+    st.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +358,8 @@ def main():
                     help="mixed: FP32 condensation; bf16: BF16-operand condensation; fp64: plain FP64")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64-1e-10, RHS-only, ordering, RAS and batched measurements")
     ap.add_argument("--dims", default="16,16,8")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--workload", default="subdomain", choices=["subdomain", "batch", "serving"])
@@ -244,13 +412,13 @@ def main():
     mesh = api.Mesh(ctx, hmesh.elem_faces(), hmesh.n_face, spec.b)
     print(f"[bench] {dims} p={args.p}: E={E} n={n} t={t} faces={hmesh.n_face} nnzb={mesh.nnzb}", file=sys.stderr,
           flush=True)
-    mats = sd.gen_blocks(spec, wl.seed, 0, E, which="ABCD")
+    mats_d = sd.gen_blocks(spec, wl.seed, 0, E, which="ABCD")
     n_rhs = wl.n_rhs
     Fs = [sd.gen_blocks(spec, wl.seed, 0, E, which="F", rhs=k)["F"] for k in range(n_rhs)]
     Gs = [sd.gen_trace_rhs(spec, wl.seed, 0, hmesh.n_face, rhs=k) for k in range(n_rhs)]
     torch.cuda.synchronize()
     print("[bench] inputs generated in HBM", file=sys.stderr, flush=True)
-    A, B, C, D = mats["A"], mats["B"], mats["C"], mats["D"]
+    A, B, C, D = mats_d["A"], mats_d["B"], mats_d["C"], mats_d["D"]
 
     results = {}
     for form in [f for f in args.forms.split(",") if f]:
@@ -301,6 +469,25 @@ def main():
         del solver
         torch.cuda.empty_cache()
 
+    extras = {}
+    if not args.no_extras:
+        mats = (A, B, C, D)
+        _log("extra: fp64 form at 1e-10")
+        extras["fp64_rtol_1e-10"] = extra_fp64_tight(ctx, mesh, n, mats, Fs, Gs, wl.restart)
+        _log("extra: rhs-only solves with retained factors")
+        extras["rhs_solves"] = extra_rhs_solves(ctx, mesh, n, mats, Fs, Gs, wl.restart)
+        _log("extra: orderings (natural, colour, mdf)")
+        extras["orderings_fp64_rtol_1e-10"] = extra_orderings(ctx, hmesh, spec, mats, Fs[0], Gs[0], wl.restart)
+        _log("extra: restricted additive Schwarz")
+        extras["ras_fp64_rtol_1e-10"] = extra_ras(ctx, hmesh, spec, mats, Fs[0], Gs[0], wl.restart)
+        del A, B, C, D, mats, mats_d, Fs, Gs
+        torch.cuda.empty_cache()
+        from paper_1605_01020_amd import F64 as _F64
+        _log("extra: batched form, FP32-mixed and FP64")
+        bf = {"f32": batch_form(ctx, F32, args), "f64": batch_form(ctx, _F64, args)}
+        bf["speedup_mixed_vs_fp64"] = bf["f32"]["solves_per_s"] / bf["f64"]["solves_per_s"]
+        extras["batch_24_meshes"] = bf
+
     head = "mixed" if "mixed" in results else "fp64"
     r = results[head]
     flops = condense_flops(n, t) * E
@@ -308,8 +495,7 @@ def main():
     achieved = flops / (r["condense_ms"] * 1e-3) / 1e12
     traffic = None
     if head == "mixed" and dims == (16, 16, 8) and args.p == 3:
-        traffic = measured_traffic(["paper_1605_01020_amd/csrc/condense.hip", "paper_1605_01020_amd/tuning.json"],
-                                   "condense_f32_16x16x8_p3_hbm_traffic.md")
+        traffic = measured_traffic(CONDENSE_SOURCES, "condense_f32_16x16x8_p3_hbm_traffic.md")
     out = {
         "metric": "Newton-step solves/s at relative residual 1e-8 (mixed FP32/FP64 form; FP64 form beside it)",
         "value": r["solves_per_s"],
@@ -333,6 +519,7 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops},
     }
+    out.update(extras)
     if "fp64" in results and "mixed" in results:
         out["speedup_mixed_vs_fp64"] = results["mixed"]["solves_per_s"] / results["fp64"]["solves_per_s"]
     if "fp64" in results and "bf16" in results:

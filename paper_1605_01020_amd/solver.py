@@ -134,6 +134,15 @@ class NewtonStepSolver:
         info["converged_full"] = hist[-1] <= tol
         return z, uhat, info
 
+    def solve_rhs_mixed(self, A, B, C, D, F, G, tol=1e-8, inner_rtol=1e-6):
+        """New right-hand side with the retained low-precision factors, then
+        FP64 refinement against the true element matrices."""
+        w, r = api.condense_rhs(self.ctx, self.fac, F, prec=self.prec)
+        _, R = api.assemble(self.ctx, self.mesh, r=r, G=G, prec=self.prec)
+        uhat, info = self._trace_solve(R, inner_rtol)
+        z = api.backsolve_local(self.ctx, self.mesh, self.fac, uhat, prec=self.prec, w=w)
+        return self.refine(A, B, C, D, F, G, z, uhat, tol, info=info)
+
     def solve_mixed(self, A, B, C, D, F, G, tol=1e-8, prec=F32, inner_rtol=1e-6, timer=None):
         timer = timer or StepTimer(False)
         timer.mark("start")

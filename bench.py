@@ -495,7 +495,7 @@ def main():
     achieved = flops / (r["condense_ms"] * 1e-3) / 1e12
     traffic = None
     if head == "mixed" and dims == (16, 16, 8) and args.p == 3:
-        traffic = measured_traffic(CONDENSE_SOURCES, "condense_f32_16x16x8_p3_hbm_traffic.md")
+        traffic = measured_traffic(CONDENSE_SOURCES, "hbm_traffic_16x16x8_p3.md")
     out = {
         "metric": "Newton-step solves/s at relative residual 1e-8 (mixed FP32/FP64 form; FP64 form beside it)",
         "value": r["solves_per_s"],

@@ -177,39 +177,70 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_serving(args):
+def serving_sweep(ctx, fracs, n_warm, n_meas, slots, budget_gb, n_cap=None, log=_log):
+    """The serving form over the 64 simulations of the uneven distribution:
+    closed-loop capacity first (every request available at once, after a
+    warm-up that fills the residency cache), then Poisson arrivals at each
+    fraction of that capacity; latency and hit rate over the measured
+    requests only (the first n_warm of each stream warm the cache)."""
     import numpy as np
-    import torch
-    from paper_1605_01020_amd import api, F32
+    from paper_1605_01020_amd import F32
     from paper_1605_01020_amd.serve import Server, poisson_requests, summarize
-    from paper_1605_01020_amd.autotune import apply_tuning
     from synth.matrices import workload
     wl = workload(4)
+    n_cap = n_meas if n_cap is None else n_cap
+    srv = Server(ctx, wl.meshes, wl.seed, budget_bytes=budget_gb * 1e9, n_slots=slots, prec=F32,
+                 restart=wl.restart, tol=wl.rtol)
+    out = {"simulations": len(wl.meshes), "slots": slots, "budget_gb": budget_gb,
+           "static_gb": srv.static_bytes / 1e9}
+    reqs = poisson_requests(wl.seed, n_warm + n_cap, 1e6, len(wl.meshes))
+    srv.run(reqs[:n_warm], real_time=False)
+    t0 = time.perf_counter()
+    done = srv.run(reqs[n_warm:], real_time=False)
+    cap = len(done) / (time.perf_counter() - t0)
+    out["capacity_solves_per_s"] = cap
+    out["capacity_hit_rate"] = sum(1 for r in done if r.hit) / len(done)
+    log(f"serving capacity {cap:.2f} solves/s over {len(done)} requests (hit rate {out['capacity_hit_rate']:.2f})")
+    out["load"] = {}
+    for i, frac in enumerate(fracs):
+        rate = frac * cap
+        reqs = poisson_requests(wl.seed + 1 + i, n_warm + n_meas, rate, len(wl.meshes))
+        t0 = time.perf_counter()
+        done = srv.run(reqs, real_time=True)
+        elapsed = time.perf_counter() - t0
+        meas = [r for r in done if r.rid >= n_warm]
+        span = max(r.done for r in meas) - min(r.arrival for r in meas)
+        s = summarize(meas, span)
+        s["rate_per_s"] = rate
+        out["load"][f"{frac:.1f}"] = s
+        log(f"load {frac:.1f} x capacity ({rate:.2f}/s): {s['solves_per_s']:.2f} solves/s, p50 {s['p50_ms']:.0f} ms, "
+            f"p99 {s['p99_ms']:.0f} ms, hit rate {s['hit_rate']:.2f} ({elapsed:.0f} s)")
+    out["stats"] = dict(srv.stats)
+    srv.close()
+    return out
+
+
+def bench_serving(args):
+    import torch
+    from paper_1605_01020_amd import api
+    from paper_1605_01020_amd.autotune import apply_tuning
     torch.cuda.set_device(0)
     ctx = api.Context(0)
     apply_tuning(ctx)
-    reqs = poisson_requests(wl.seed, args.requests, args.rate, len(wl.meshes))
-    srv = Server(ctx, wl.meshes, wl.seed, budget_bytes=args.budget_gb * 1e9, n_slots=args.slots, prec=F32,
-                 restart=wl.restart, tol=wl.rtol)
-    _log(f"serving {len(reqs)} requests at {args.rate}/s over {len(wl.meshes)} simulations, "
-         f"{args.slots} slots, budget {args.budget_gb} GB")
-    t0 = time.perf_counter()
-    done = srv.run(reqs, real_time=True)
-    elapsed = time.perf_counter() - t0
-    s = summarize(done, elapsed)
-    stats = dict(srv.stats)
-    srv.close()
+    fracs = [float(f) for f in args.loads.split(",")]
+    res = serving_sweep(ctx, fracs, args.serve_warmup, args.requests, args.slots, args.budget_gb)
+    head = res["load"][f"{fracs[len(fracs) // 2]:.1f}"]
     line = {
         "metric": "Newton-step solves/s at relative residual 1e-8 with p50/p99 latency, serving form",
-        "value": s["solves_per_s"], "unit": "Newton-step solves/s", "n_gpus": 1, "steps": len(done), "warmup": 0,
-        "ms_per_step": elapsed * 1e3 / len(done), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (seeded Poisson arrivals and Philox matrices)",
-        "config": {"workload": f"{len(wl.meshes)} simulations from the uneven batch distribution, Poisson "
-                               f"arrivals at {args.rate}/s, {args.requests} requests, budget {args.budget_gb} GB, "
-                               f"{args.slots} stream slots",
-                   "rate_per_s": args.rate},
-        "lat_ms": {"p50": s["p50_ms"], "p99": s["p99_ms"]},
-        "hit_rate": s["hit_rate"], "max_rho_full": s["max_rho"], **stats,
+        "value": head["solves_per_s"], "unit": "Newton-step solves/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": args.serve_warmup, "ms_per_step": 1e3 / head["solves_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic (seeded Poisson arrivals and Philox matrices)",
+        "config": {"workload": f"{res['simulations']} simulations from the uneven batch distribution, Poisson "
+                               f"arrivals at {fracs} x measured capacity, {args.serve_warmup} warm-up + "
+                               f"{args.requests} measured requests per load, budget {args.budget_gb} GB, "
+                               f"{args.slots} stream slots"},
+        "serving": res,
     }
     print(json.dumps(line), flush=True)
 
@@ -364,8 +395,9 @@ def main():
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--workload", default="subdomain", choices=["subdomain", "batch", "serving"])
     ap.add_argument("--budget-gb", type=float, default=200.0)
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--rate", type=float, default=4.0)
+    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests per load")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="serving: warm-up requests per load")
+    ap.add_argument("--loads", default="0.5,0.7,0.9", help="serving: arrival rates as fractions of capacity")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="first run a plain device copy of this many GiB (reference for HBM counters)")
@@ -487,6 +519,8 @@ def main():
         bf = {"f32": batch_form(ctx, F32, args), "f64": batch_form(ctx, _F64, args)}
         bf["speedup_mixed_vs_fp64"] = bf["f32"]["solves_per_s"] / bf["f64"]["solves_per_s"]
         extras["batch_24_meshes"] = bf
+        _log("extra: serving form (reduced: 0.7 x capacity, 40 warm-up + 120 measured requests)")
+        extras["serving_reduced"] = serving_sweep(ctx, [0.7], 40, 120, args.slots, args.budget_gb, n_cap=80)
 
     head = "mixed" if "mixed" in results else "fp64"
     r = results[head]

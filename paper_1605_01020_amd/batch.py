@@ -63,7 +63,11 @@ class Simulation:
     buffers of the solve and of its refinement."""
 
     def __init__(self, ctx, case, seed, prec=F32, restart=100, n_refine=1, tol=1e-8, inner_rtol=1e-6,
-                 correction_rtol=1e-3, ordering="colour", cycle_steps=24):
+                 correction_rtol=1e-3, ordering="colour", cycle_steps=24, allocate=True):
+        """The mesh and the GMRES workspaces are created here and kept for the
+        simulation's lifetime; the per-solve arrays (inputs, factors, trace
+        system, vectors) live in one byte arena that attach() carves up and
+        detach() hands back (allocate=False: no arena yet)."""
         from synth.mesh import StructuredHexMesh
         self.ctx, self.case, self.seed, self.prec = ctx, case, seed, prec
         self.tol, self.inner_rtol, self.correction_rtol = tol, inner_rtol, correction_rtol
@@ -73,29 +77,6 @@ class Simulation:
         self.spec = spec
         self.E, self.n, self.t, self.b = hm.n_elem, spec.n, spec.t, spec.b
         self.mesh = api.Mesh(ctx, hm.elem_faces(), hm.n_face, spec.b, ordering=ordering)
-        E, n, t, dev = self.E, self.n, self.t, torch.device("cuda")
-        N_t = self.mesh.n_trace
-        f64 = dict(dtype=torch.float64, device=dev)
-        self.inp = {"A": torch.empty((E, n, n), **f64), "B": torch.empty((E, n, t), **f64),
-                    "C": torch.empty((E, t, n), **f64), "D": torch.empty((E, t, t), **f64),
-                    "F": torch.empty((E, n), **f64)}
-        self.G = torch.empty(N_t, **f64)
-        self.fac = api.alloc_condense_out(E, n, t, prec, dev)
-        dt = api.PREC_DTYPE[prec]
-        self.K = torch.empty((self.mesh.nnzb, self.b, self.b), dtype=dt, device=dev)
-        self.M = torch.empty_like(self.K)
-        self.R = torch.empty(N_t, **f64)
-        self.uhat = torch.empty(N_t, **f64)
-        self.z = torch.empty((E, n), **f64)
-        self.rF = torch.empty((E, n), **f64)
-        self.rG = torch.empty(N_t, **f64)
-        self.wc = torch.empty((E, n), **f64)
-        self.rc = torch.empty((E, t), **f64)
-        self.Rc = torch.empty(N_t, **f64)
-        self.du = torch.empty(N_t, **f64)
-        self.dz = torch.empty((E, n), **f64)
-        # one residual-sum slot per refinement residual (stage 0 .. n_refine)
-        self.sums = torch.zeros((n_refine + 1, 4), **f64)
         # device-driven cycles stop at cycle_steps Arnoldi steps (every step
         # is enqueued, later ones return at once after convergence); a cycle
         # that stops unconverged is continued by the refinement on the host
@@ -103,6 +84,65 @@ class Simulation:
         self.gm = [api.GmresState(ctx, self.mesh, min(restart, cycle_steps if s == 0 else max(8, cycle_steps // 2)))
                    for s in range(n_refine + 1)]
         self.restart = restart
+        self.arena = None
+        if allocate:
+            self.attach(torch.empty(self.arena_bytes(), dtype=torch.uint8, device="cuda"))
+
+    def _layout(self):
+        """(name, shape, dtype) of every per-solve array."""
+        E, n, t, N_t = self.E, self.n, self.t, self.mesh.n_trace
+        f64, i32, lo = torch.float64, torch.int32, api.PREC_DTYPE[self.prec]
+        return [("A", (E, n, n), f64), ("B", (E, n, t), f64), ("C", (E, t, n), f64), ("D", (E, t, t), f64),
+                ("F", (E, n), f64), ("G", (N_t,), f64),
+                ("LU", (E, n, n), lo), ("perm", (E, n), i32), ("U12", (E, n, t), lo), ("L21", (E, t, n), lo),
+                ("Ke", (E, t, t), lo), ("w", (E, n), f64), ("r", (E, t), f64),
+                ("K", (self.mesh.nnzb, self.b, self.b), lo), ("M", (self.mesh.nnzb, self.b, self.b), lo),
+                ("R", (N_t,), f64), ("uhat", (N_t,), f64), ("z", (E, n), f64), ("rF", (E, n), f64),
+                ("rG", (N_t,), f64), ("wc", (E, n), f64), ("rc", (E, t), f64), ("Rc", (N_t,), f64),
+                ("du", (N_t,), f64), ("dz", (E, n), f64), ("sums", (self.n_refine + 1, 4), f64)]
+
+    @staticmethod
+    def _nbytes(shape, dtype):
+        k = 1
+        for d in shape:
+            k *= d
+        return k * torch.empty((), dtype=dtype).element_size()
+
+    def arena_bytes(self):
+        return sum((self._nbytes(sh, dt) + 255) // 256 * 256 for _, sh, dt in self._layout())
+
+    def attach(self, arena):
+        """Carve the per-solve arrays out of `arena` (a uint8 device tensor of
+        at least arena_bytes(), every array on a 256-byte boundary)."""
+        if arena.numel() < self.arena_bytes():
+            raise ValueError("arena too small")
+        views, off = {}, 0
+        for name, shape, dt in self._layout():
+            nb = self._nbytes(shape, dt)
+            views[name] = arena[off:off + nb].view(dt).view(shape)
+            off += (nb + 255) // 256 * 256
+        self.arena = arena
+        self.inp = {k: views[k] for k in "ABCDF"}
+        self.G = views["G"]
+        self.fac = {k: views[k] for k in ("LU", "perm", "U12", "L21", "Ke", "w", "r")}
+        for k in ("K", "M", "R", "uhat", "z", "rF", "rG", "wc", "rc", "Rc", "du", "dz", "sums"):
+            setattr(self, k, views[k])
+        self.sums.zero_()
+
+    def detach(self):
+        """Give the arena back (the simulation keeps its mesh and workspaces)."""
+        arena = self.arena
+        self.arena = None
+        for k in ("inp", "G", "fac", "K", "M", "R", "uhat", "z", "rF", "rG", "wc", "rc", "Rc", "du", "dz", "sums"):
+            if hasattr(self, k):
+                delattr(self, k)
+        return arena
+
+    def static_bytes(self):
+        """Device bytes held for the whole lifetime (the GMRES workspaces; the
+        mesh's index arrays and residual scratch are small beside them)."""
+        ldv = (self.mesh.n_trace + 63) // 64 * 64
+        return sum(8 * (g.steps + 3) * ldv for g in self.gm)
 
     @staticmethod
     def footprint(case, prec=F32, restart=100, n_refine=1):
@@ -216,6 +256,7 @@ class Simulation:
         for g in self.gm:
             g.close()
         self.gm = []
+        self.detach()
         self.mesh.close()
 
 

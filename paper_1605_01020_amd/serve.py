@@ -40,6 +40,7 @@ class Request:
     rho: float = None
     iters: int = None
     eager_steps: int = 0
+    error: str = None
     uhat: torch.Tensor = None
     z: torch.Tensor = None
 
@@ -69,15 +70,27 @@ def poisson_requests(seed, n_requests, rate, n_sims):
 
 
 class _Slot:
-    def __init__(self):
+    def __init__(self, device):
         self.stream = torch.cuda.Stream()
+        # a context per slot: a device error latched by a request fails that
+        # request alone
+        self.ctx = api.Context(device)
         self.event = None
         self.req = None
         self.sums_host = None
 
 
 class Server:
-    """Request loop over `cases` (one simulation per case)."""
+    """Request loop over `cases` (one simulation per case).
+
+    Every simulation's mesh and GMRES workspaces are created up front (small
+    and fixed); its per-solve arrays (FP64 element matrices, factors, trace
+    system, vectors) live in a byte arena while it is resident.  Admission
+    takes the smallest free arena that fits, else a new one within the
+    budget, else evicts idle residents (least recently used first), whose
+    arenas go to the free list rather than back to the allocator, so the
+    request loop itself allocates and frees no device memory once the pool
+    has formed."""
 
     def __init__(self, ctx, cases, seed, budget_bytes=200e9, n_slots=4, prec=F32, restart=100, tol=1e-8,
                  n_refine=1, keep_results=False):
@@ -85,51 +98,73 @@ class Server:
         self.budget = float(budget_bytes)
         self.prec, self.restart, self.tol, self.n_refine = prec, restart, tol, n_refine
         self.keep = keep_results
-        self.slots = [_Slot() for _ in range(n_slots)]
-        self.resident = OrderedDict()      # sim id -> Simulation, least recently used first
-        self.bytes = {}                    # sim id -> admitted bytes
+        dev = torch.cuda.current_device()
+        self.slots = [_Slot(dev) for _ in range(n_slots)]
+        self.sims = [Simulation(ctx, c, seed, prec=prec, restart=restart, n_refine=n_refine, tol=tol,
+                                allocate=False) for c in self.cases]
+        self.static_bytes = sum(s.static_bytes() for s in self.sims)
+        self.need = [s.arena_bytes() for s in self.sims]
+        self.arena_budget = self.budget - self.static_bytes
+        for sid, nb in enumerate(self.need):
+            if nb > self.arena_budget:
+                raise ValueError(f"simulation {sid} needs {nb / 1e9:.1f} GB > budget")
+        self.resident = OrderedDict()      # sim id -> None, least recently used first
+        self.free = []                     # idle arenas
+        self.allocated = 0                 # bytes of all arenas (resident and idle)
         self.busy = set()
-        self.used = 0.0
-        self.stats = {"hits": 0, "misses": 0, "evictions": 0}
-        self._fp = [Simulation.footprint(c, prec, restart, n_refine) for c in self.cases]
-        for f, c in zip(self._fp, self.cases):
-            if f > self.budget:
-                raise ValueError(f"simulation {c.mesh_id} needs {f / 1e9:.1f} GB > budget")
+        self.stats = {"hits": 0, "misses": 0, "evictions": 0, "arenas_allocated": 0, "arenas_reused": 0,
+                      "arenas_dropped": 0, "failed": 0}
 
     # -- residency ------------------------------------------------------------
+    def _best_free(self, need):
+        fits = [i for i, a in enumerate(self.free) if a.numel() >= need]
+        return min(fits, key=lambda i: self.free[i].numel()) if fits else None
+
     def _can_admit(self, sid):
         if sid in self.resident:
             return True
-        need = self._fp[sid]
-        free = self.budget - self.used
-        if need <= free:
+        need = self.need[sid]
+        if self._best_free(need) is not None or self.allocated + need <= self.arena_budget:
             return True
-        idle = sum(self.bytes[s] for s in self.resident if s not in self.busy)
-        return need <= free + idle
+        idle = sum(self.sims[s].arena.numel() for s in self.resident if s not in self.busy)
+        free = sum(a.numel() for a in self.free)
+        return self.allocated - idle - free + need <= self.arena_budget
+
+    def _evict(self, s):
+        del self.resident[s]
+        self.free.append(self.sims[s].detach())
+        self.stats["evictions"] += 1
 
     def _admit(self, sid):
-        need = self._fp[sid]
-        for s in list(self.resident):
-            if self.used + need <= self.budget:
-                break
-            if s in self.busy:
-                continue
-            sim = self.resident.pop(s)
-            sim.close()
-            self.used -= self.bytes.pop(s)
-            self.stats["evictions"] += 1
-            del sim
-        assert self.used + need <= self.budget
-        # evicted simulations' blocks stay in torch's cache; give them back
-        # when the cache has grown well past the budget (limits fragmentation)
-        if torch.cuda.memory_reserved() > 1.25 * self.budget:
-            torch.cuda.empty_cache()
-        sim = Simulation(self.ctx, self.cases[sid], self.seed, prec=self.prec, restart=self.restart,
-                         n_refine=self.n_refine, tol=self.tol)
-        self.resident[sid] = sim
-        self.bytes[sid] = need
-        self.used += need
-        return sim
+        need = self.need[sid]
+        pick = self._best_free(need)
+        if pick is None and self.allocated + need > self.arena_budget:
+            for s in [s for s in self.resident if s not in self.busy]:
+                self._evict(s)
+                pick = self._best_free(need)
+                if pick is not None or self.allocated + need <= self.arena_budget:
+                    break
+        if pick is not None:
+            arena = self.free.pop(pick)
+            self.stats["arenas_reused"] += 1
+        else:
+            # drop idle arenas (smallest first) until a new one fits
+            self.free.sort(key=lambda a: a.numel())
+            while self.free and self.allocated + need > self.arena_budget:
+                self.allocated -= self.free.pop(0).numel()
+                self.stats["arenas_dropped"] += 1
+            assert self.allocated + need <= self.arena_budget
+            arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+            self.allocated += need
+            self.stats["arenas_allocated"] += 1
+        self.sims[sid].attach(arena)
+        self.resident[sid] = None
+        return self.sims[sid]
+
+    def _bind(self, sim, ctx):
+        sim.ctx = ctx
+        for g in sim.gm:
+            g.ctx = ctx
 
     # -- one request on one slot ----------------------------------------------
     def _launch(self, slot, req, now):
@@ -137,16 +172,18 @@ class Server:
         req.start = now
         with torch.cuda.stream(slot.stream):
             if sid in self.resident:
-                sim = self.resident[sid]
+                sim = self.sims[sid]
                 self.resident.move_to_end(sid)
                 req.hit = True
                 self.stats["hits"] += 1
+                self._bind(sim, slot.ctx)
                 sim.set_rhs(req.rhs)
                 sim.enqueue_rhs()
             else:
                 sim = self._admit(sid)
                 req.hit = False
                 self.stats["misses"] += 1
+                self._bind(sim, slot.ctx)
                 sim.generate(req.rhs)
                 # factor, then the same right-hand-side path as a hit: a
                 # request's result does not depend on whether it hit
@@ -166,7 +203,20 @@ class Server:
     def _complete(self, slot, now):
         req = slot.req
         req.done = now
-        sim = self.resident[req.sim]
+        sim = self.sims[req.sim]
+        try:
+            with torch.cuda.stream(slot.stream):
+                slot.ctx.sync_status()
+        except api.IedgError as err:
+            # this request fails alone; its simulation's state is suspect
+            req.error = str(err)
+            req.rho = float("nan")
+            self.stats["failed"] += 1
+            self.busy.discard(req.sim)
+            if req.sim in self.resident:
+                self._evict(req.sim)
+            slot.event = slot.req = None
+            return
         sums = slot.sums_host.tolist()
         rho = Simulation._rho(sums[-1])
         if not rho <= self.tol:
@@ -220,22 +270,23 @@ class Server:
                 progressed = True
             if not progressed:
                 time.sleep(20e-6)
-        self.ctx.sync_status()
         return done
 
     def close(self):
         torch.cuda.synchronize()
-        for sim in self.resident.values():
+        for sim in self.sims:
             sim.close()
+        self.sims = []
         self.resident.clear()
-        self.bytes.clear()
-        self.used = 0.0
+        self.free.clear()
+        self.allocated = 0
 
 
 def summarize(done, elapsed=None):
-    lat = np.array([r.latency for r in done]) * 1e3
+    ok = [r for r in done if r.error is None]
+    lat = np.array([r.latency for r in ok]) * 1e3
     span = elapsed if elapsed is not None else max(r.done for r in done) - min(r.arrival for r in done)
     return {"requests": len(done), "solves_per_s": len(done) / span if span > 0 else float("nan"),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "hit_rate": sum(1 for r in done if r.hit) / len(done),
-            "max_rho": max(r.rho for r in done)}
+            "max_rho": max(r.rho for r in ok), "failed": len(done) - len(ok)}

@@ -143,13 +143,22 @@ iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32_t n_local,
                               const double* F, double* w, double* r,
                               hipStream_t stream);
 
-/* Batched condensation (section 2.2.1, eq. LS) of several meshes whose
- * elements share (n, t): one launch over a work list of (segment,
- * element) items that interleaves the segments, each item computed exactly
- * as iedg_condense computes it (bitwise the same outputs).  The plan
- * copies the segment table to the device once; iedg_condense_batched only
- * launches (it can be captured in a HIP graph).  Segment pointers must stay
- * valid for the plan's lifetime. */
+/* Batched condensation (section 2.2.1, eq. LS) of several meshes (segments)
+ * in one persistent launch: one workgroup per CU slot takes (segment,
+ * element) items from a device queue until it is empty.  Each item is
+ * computed exactly as iedg_condense computes it (bitwise the same outputs,
+ * with the sub-panel width the context held for that size when the plan was
+ * made).  Segments may differ in element size (iedg_batch_create_sized:
+ * n_local[s], n_trace_elem[s] per segment, each a size iedg_condense
+ * accepts); the work list starts with the largest elements and interleaves
+ * the segments of one size.  The plan copies the segment table and work list
+ * to the device once; iedg_condense_batched only launches (a reset kernel
+ * and the condensation; it can be captured in a HIP graph).  Calls with one
+ * plan must not overlap (they share the queue counter).  Segment pointers
+ * must stay valid for the plan's lifetime.  iedg_batch_create is the
+ * one-size form.  Errors: IEDG_ERR_INVALID_ARG (sizes, null or unaligned
+ * arrays of a segment with elements), IEDG_ERR_UNSUPPORTED (size or
+ * precision), IEDG_ERR_HIP / IEDG_ERR_OOM from the uploads. */
 typedef struct {
   int32_t n_elem;
   const double *A, *B, *C, *D, *F;
@@ -164,6 +173,10 @@ typedef struct iedg_batch_s* iedg_batch;
 iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
                               int32_t n_local, int32_t n_trace_elem, iedg_prec prec,
                               iedg_batch* out);
+iedg_status iedg_batch_create_sized(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
+                                    const int32_t* n_local /* host, [n_seg] */,
+                                    const int32_t* n_trace_elem /* host, [n_seg] */, iedg_prec prec,
+                                    iedg_batch* out);
 iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch batch, hipStream_t stream);
 void iedg_batch_destroy(iedg_batch batch);
 /* Tuning of the condensation kernel: width of the register-resident

@@ -53,6 +53,8 @@ SIGNATURES = {
                                 P, P, P, P, P, P, P, P]),
     "iedg_batch_create": (c_int32, [P, c_int32, ctypes.POINTER(CondenseSegment), c_int32, c_int32,
                                     c_int32, ctypes.POINTER(c_void_p)]),
+    "iedg_batch_create_sized": (c_int32, [P, c_int32, ctypes.POINTER(CondenseSegment), P, P,
+                                          c_int32, ctypes.POINTER(c_void_p)]),
     "iedg_condense_batched": (c_int32, [P, P, P]),
     "iedg_batch_destroy": (None, [P]),
     "iedg_set_leaf_width": (c_int32, [P, c_int32, c_int32, c_int32]),

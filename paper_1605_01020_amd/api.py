@@ -161,34 +161,35 @@ def alloc_condense_out(E, n, t, prec, device, with_rhs=True):
 
 
 class CondenseBatch:
-    """Plan for one condensation launch over several segments
-    (meshes) with the same element size (iedg_batch_*).  `segments` is a
-    list of (inputs, outputs) dicts: inputs A, B, C, D, F (F may be None),
-    outputs as from alloc_condense_out.  Tensors must outlive the plan."""
+    """Plan for one persistent condensation launch over several segments
+    (meshes), of one element size or of several (iedg_batch_create_sized).
+    `segments` is a list of (inputs, outputs) dicts: inputs A, B, C, D, F (F
+    may be None), outputs as from alloc_condense_out.  Tensors must outlive
+    the plan."""
 
     def __init__(self, ctx, segments, prec=F64):
         self.ctx = ctx
         self._keep = segments
-        arr = (CondenseSegment * len(segments))()
-        n = t = None
+        k = len(segments)
+        arr = (CondenseSegment * k)()
+        ns = (ctypes.c_int32 * k)()
+        ts = (ctypes.c_int32 * k)()
         for i, (inp, out) in enumerate(segments):
             _check_dev(inp["A"], inp["B"], inp["C"], inp["D"], inp.get("F"))
-            E, n_i, _ = inp["A"].shape
-            t_i = inp["B"].shape[2]
-            if n is None:
-                n, t = n_i, t_i
-            elif (n, t) != (n_i, t_i):
-                raise ValueError("all segments of a batch share (n, t)")
+            E, ns[i], _ = inp["A"].shape
+            ts[i] = inp["B"].shape[2]
             a = arr[i]
             a.n_elem = E
-            a.A, a.B, a.C, a.D = (inp[k].data_ptr() for k in "ABCD")
+            a.A, a.B, a.C, a.D = (inp[key].data_ptr() for key in "ABCD")
             a.F = inp["F"].data_ptr() if inp.get("F") is not None else None
-            a.LU, a.perm, a.U12, a.L21, a.Ke = (out[k].data_ptr() for k in ("LU", "perm", "U12", "L21", "Ke"))
+            a.LU, a.perm, a.U12, a.L21, a.Ke = (out[key].data_ptr() for key in ("LU", "perm", "U12", "L21", "Ke"))
             a.w = out["w"].data_ptr() if "w" in out else None
             a.r = out["r"].data_ptr() if "r" in out else None
         h = ctypes.c_void_p()
-        ctx.check(ctx.L.iedg_batch_create(ctx.h, len(segments), arr, n, t, prec, ctypes.byref(h)))
-        self.h, self.n, self.t, self.prec = h, n, t, prec
+        ctx.check(ctx.L.iedg_batch_create_sized(ctx.h, k, arr, ctypes.cast(ns, ctypes.c_void_p),
+                                                ctypes.cast(ts, ctypes.c_void_p), prec, ctypes.byref(h)))
+        self.h, self.prec = h, prec
+        self.sizes = sorted({(ns[i], ts[i]) for i in range(k)}, reverse=True)
 
     def run(self):
         self.ctx.check(self.ctx.L.iedg_condense_batched(self.ctx.h, self.h, _stream()))

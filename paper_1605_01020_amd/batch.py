@@ -273,16 +273,17 @@ def _nnzb_estimate(hm):
 
 
 class BatchGroup:
-    """Meshes solved together: one condensation launch per element
-    size, then every mesh's trace solve; optionally captured in a graph."""
+    """Meshes solved together: one persistent condensation launch over
+    every mesh of a precision (all element sizes), then every mesh's trace
+    solve; optionally captured in a graph."""
 
     def __init__(self, ctx, sims):
         self.ctx, self.sims = ctx, sims
-        by_size = {}
+        by_prec = {}
         for s in sims:
-            by_size.setdefault((s.n, s.t, s.prec), []).append(s)
-        self.plans = [api.CondenseBatch(ctx, [s.condense_segment() for s in group], prec=key[2])
-                      for key, group in sorted(by_size.items())]
+            by_prec.setdefault(s.prec, []).append(s)
+        self.plans = [api.CondenseBatch(ctx, [s.condense_segment() for s in group], prec=prec)
+                      for prec, group in sorted(by_prec.items())]
         self.graph = None
 
     def enqueue(self):

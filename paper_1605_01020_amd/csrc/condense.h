@@ -13,18 +13,44 @@ struct CondenseArgs {
   int32_t* perm;
   double *w, *r;
   DeviceStatus* status;
+  int lw;  // sub-panel width (8 or 16) of this segment in the batched form
 };
 
-// One condensation launch (segs == nullptr: elements 0 .. a.E-1 of `a`;
-// otherwise one workgroup per (segment, element) item).  lw: sub-panel
-// width 8 or 16, 0 for the untuned default.  Each is defined in the
-// translation unit of its precision.
-hipError_t condense_launch_f64(const CondenseArgs<double>& a, const CondenseArgs<double>* segs, const int2* items,
-                               int n_items, int lw, hipStream_t s);
-hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const int2* items,
-                               int n_items, int lw, hipStream_t s);
-hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const int2* items,
-                                int n_items, int lw, hipStream_t s);
+// The persistent batched form: n_wg workgroups take n_items (segment,
+// element) items from a queue (counter: one device int, reset by the
+// launch on the stream); LDS is sized for elements of up to n_max local dofs.
+struct QueueLaunch {
+  const int2* items;
+  int n_items, n_max, n_wg;
+  int* counter;
+};
+
+// One condensation launch.  segs == nullptr: elements 0 .. a.E-1 of `a`, one
+// workgroup each, sub-panel width lw (8 or 16; 0 for the untuned default).
+// Otherwise the batched form over segs as described by q (a, lw unused).
+// Each is defined in the translation unit of its precision.
+hipError_t condense_launch_f64(const CondenseArgs<double>& a, const CondenseArgs<double>* segs, const QueueLaunch& q,
+                               int lw, hipStream_t s);
+hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q,
+                               int lw, hipStream_t s);
+hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q,
+                                int lw, hipStream_t s);
+
+// Persistent grid size of the batched form for LDS sized for n_max local
+// dofs (0 on a HIP error), per precision.
+int condense_queue_slots_f64(int n_max);
+int condense_queue_slots_f32(int n_max);
+int condense_queue_slots_bf16(int n_max);
+
+// Untuned sub-panel width for elements of n local dofs and t trace dofs
+// (512 threads, so q rows of A and C per thread): 16 where q x 16 register
+// values stay within the register file without spilling (FP32 up to 4 rows
+// per thread, FP64 up to 2), else 8.
+inline int default_leaf_width(size_t elem_bytes, int n, int t) {
+  const int qa = (n + 511) / 512, qc = (t + 511) / 512;
+  const int q = (qa <= 1 && qc <= 1) ? 2 : (qa <= 3 && qc <= 1) ? 4 : 7;
+  return (elem_bytes == 8 ? q <= 2 : q <= 4) ? 16 : 8;
+}
 
 // Largest n and t the kernel is built for (rows per thread: 5 of A, 2 of C).
 constexpr int kCondenseMaxN = 5 * 512, kCondenseMaxT = 2 * 512;

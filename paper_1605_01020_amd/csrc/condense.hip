@@ -131,14 +131,14 @@ extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n
   hipError_t err;
   if (prec == IEDG_F64) {
     CondenseArgs<double> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
-                           (double*)LU, (double*)U12, (double*)L21, (double*)Ke, perm, w, r, ctx->d_status};
-    err = condense_launch_f64(a, nullptr, nullptr, 0, leaf_width(ctx, prec, n_local), stream);
+                           (double*)LU, (double*)U12, (double*)L21, (double*)Ke, perm, w, r, ctx->d_status, 0};
+    err = condense_launch_f64(a, nullptr, QueueLaunch{}, leaf_width(ctx, prec, n_local), stream);
   } else if (prec == IEDG_F32 || prec == IEDG_BF16) {
     CondenseArgs<float> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
-                          (float*)LU, (float*)U12, (float*)L21, (float*)Ke, perm, w, r, ctx->d_status};
+                          (float*)LU, (float*)U12, (float*)L21, (float*)Ke, perm, w, r, ctx->d_status, 0};
     const int lw = leaf_width(ctx, prec, n_local);
-    err = prec == IEDG_F32 ? condense_launch_f32(a, nullptr, nullptr, 0, lw, stream)
-                           : condense_launch_bf16(a, nullptr, nullptr, 0, lw, stream);
+    err = prec == IEDG_F32 ? condense_launch_f32(a, nullptr, QueueLaunch{}, lw, stream)
+                           : condense_launch_bf16(a, nullptr, QueueLaunch{}, lw, stream);
   } else {
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: precision %d not built", (int)prec);
   }
@@ -177,56 +177,84 @@ extern "C" iedg_status iedg_condense_rhs(iedg_context ctx, int32_t n_elem, int32
 // ---- batched condensation ---------------------------------------------------
 struct iedg_batch_s {
   iedg_context ctx = nullptr;
-  int n = 0, t = 0, n_items = 0;
+  int n_max = 0, n_items = 0, n_wg = 0;
   iedg_prec prec = IEDG_F64;
   void* d_segs = nullptr;   // CondenseArgs<T>[n_seg]
   int2* d_items = nullptr;  // (segment, element) work list
-  CondenseArgs<double> proto64{};
-  CondenseArgs<float> proto32{};
+  int* d_counter = nullptr; // queue position of the persistent launch
 };
 
-extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
-                                         int32_t n_local, int32_t n_trace_elem, iedg_prec prec, iedg_batch* out) {
-  if (!ctx || !out || n_seg <= 0 || !segs || n_local <= 0 || n_trace_elem <= 0)
+extern "C" iedg_status iedg_batch_create_sized(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
+                                               const int32_t* n_local, const int32_t* n_trace_elem, iedg_prec prec,
+                                               iedg_batch* out) {
+  if (!ctx || !out || n_seg <= 0 || !segs || !n_local || !n_trace_elem)
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: bad arguments");
-  if ((n_local & 3) || (n_trace_elem & 1) || n_local > kCondenseMaxN || n_trace_elem > kCondenseMaxT)
-    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: n=%d t=%d", n_local, n_trace_elem);
   if (prec != IEDG_F64 && prec != IEDG_F32 && prec != IEDG_BF16)
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: precision");
   *out = nullptr;
-  std::vector<int2> items;
   std::vector<CondenseArgs<double>> a64;
   std::vector<CondenseArgs<float>> a32;
-  // items interleave the segments so that concurrently running workgroups
-  // work on different meshes' memory
-  int maxE = 0;
+  int n_max = 0;
   for (int s = 0; s < n_seg; ++s) {
     const iedg_condense_segment& g = segs[s];
+    const int n = n_local[s], t = n_trace_elem[s];
+    if (n <= 0 || t <= 0) return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d sizes", s);
+    if ((n & 3) || (t & 1) || n > kCondenseMaxN || t > kCondenseMaxT)
+      return set_error(ctx, IEDG_ERR_UNSUPPORTED, "batch_create: segment %d n=%d t=%d", s, n, t);
     if (g.n_elem < 0 || (g.n_elem > 0 && (!g.A || !g.B || !g.C || !g.D || !g.LU || !g.perm || !g.U12 || !g.L21 || !g.Ke)))
       return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d incomplete", s);
     if (g.F && (!g.w || !g.r)) return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d F without w, r", s);
     if (!aligned16({g.A, g.B, g.C, g.D, g.F, g.LU, g.perm, g.U12, g.L21, g.w, g.Ke, g.r}))
       return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d arrays must be 16-byte aligned", s);
-    maxE = std::max(maxE, (int)g.n_elem);
-    a64.push_back(CondenseArgs<double>{g.n_elem, n_local, n_trace_elem, g.A, g.B, g.C, g.D, g.F, (double*)g.LU,
-                                       (double*)g.U12, (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r,
-                                       ctx->d_status});
-    a32.push_back(CondenseArgs<float>{g.n_elem, n_local, n_trace_elem, g.A, g.B, g.C, g.D, g.F, (float*)g.LU,
-                                      (float*)g.U12, (float*)g.L21, (float*)g.Ke, g.perm, g.w, g.r,
-                                      ctx->d_status});
+    // the width iedg_condense would use for this size now (context table or default)
+    int lw = leaf_width(ctx, prec, n);
+    if (lw == 0) lw = default_leaf_width(prec == IEDG_F64 ? 8 : 4, n, t);
+    if (g.n_elem > 0) n_max = std::max(n_max, n);
+    a64.push_back(CondenseArgs<double>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (double*)g.LU, (double*)g.U12,
+                                       (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw});
+    a32.push_back(CondenseArgs<float>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (float*)g.LU, (float*)g.U12,
+                                      (float*)g.L21, (float*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw});
   }
-  for (int e = 0; e < maxE; ++e)
-    for (int s = 0; s < n_seg; ++s)
-      if (e < segs[s].n_elem) items.push_back(make_int2(s, e));
+  // Work list: size classes from the largest element down (the long items
+  // start first, the persistent workgroups finish on short ones); within a
+  // class the segments interleave, so that concurrently running workgroups
+  // read different meshes' memory.
+  std::vector<int> seg_order(n_seg);
+  for (int s = 0; s < n_seg; ++s) seg_order[s] = s;
+  std::stable_sort(seg_order.begin(), seg_order.end(), [&](int x, int y) {
+    return n_local[x] != n_local[y] ? n_local[x] > n_local[y] : n_trace_elem[x] > n_trace_elem[y];
+  });
+  std::vector<int2> items;
+  for (size_t c0 = 0; c0 < seg_order.size();) {
+    size_t c1 = c0;
+    int maxE = 0;
+    while (c1 < seg_order.size() && n_local[seg_order[c1]] == n_local[seg_order[c0]] &&
+           n_trace_elem[seg_order[c1]] == n_trace_elem[seg_order[c0]])
+      maxE = std::max(maxE, (int)segs[seg_order[c1++]].n_elem);
+    for (int e = 0; e < maxE; ++e)
+      for (size_t k = c0; k < c1; ++k)
+        if (e < segs[seg_order[k]].n_elem) items.push_back(make_int2(seg_order[k], e));
+    c0 = c1;
+  }
   auto* b = new iedg_batch_s();
   b->ctx = ctx;
-  b->n = n_local;
-  b->t = n_trace_elem;
+  b->n_max = n_max;
   b->prec = prec;
   b->n_items = (int)items.size();
+  if (!items.empty()) {
+    const int slots = prec == IEDG_F64   ? condense_queue_slots_f64(n_max)
+                      : prec == IEDG_F32 ? condense_queue_slots_f32(n_max)
+                                         : condense_queue_slots_bf16(n_max);
+    if (slots <= 0) {
+      delete b;
+      return set_error(ctx, IEDG_ERR_HIP, "batch_create: no occupancy for n=%d", n_max);
+    }
+    b->n_wg = std::min(slots, b->n_items);
+  }
   const size_t seg_bytes = prec == IEDG_F64 ? a64.size() * sizeof(a64[0]) : a32.size() * sizeof(a32[0]);
   hipError_t e = hipMalloc(&b->d_segs, seg_bytes);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_items), std::max<size_t>(1, items.size()) * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->d_counter), sizeof(int));
   if (e == hipSuccess)
     e = hipMemcpy(b->d_segs, prec == IEDG_F64 ? (const void*)a64.data() : (const void*)a32.data(), seg_bytes,
                   hipMemcpyHostToDevice);
@@ -236,26 +264,28 @@ extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const 
     iedg_batch_destroy(b);
     return hip_check(ctx, e, "batch_create upload");
   }
-  b->proto64 = a64[0];
-  b->proto32 = a32[0];
   *out = b;
   return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_batch_create(iedg_context ctx, int32_t n_seg, const iedg_condense_segment* segs,
+                                         int32_t n_local, int32_t n_trace_elem, iedg_prec prec, iedg_batch* out) {
+  if (!ctx || !out || n_seg <= 0 || !segs) return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: bad arguments");
+  std::vector<int32_t> ns(n_seg, n_local), ts(n_seg, n_trace_elem);
+  return iedg_batch_create_sized(ctx, n_seg, segs, ns.data(), ts.data(), prec, out);
 }
 
 extern "C" iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch b, hipStream_t stream) {
   if (!ctx || !b) return IEDG_ERR_INVALID_ARG;
   if (b->n_items == 0) return IEDG_OK;
+  const QueueLaunch q{b->d_items, b->n_items, b->n_max, b->n_wg, b->d_counter};
   hipError_t err;
-  const int lw = leaf_width(ctx, b->prec, b->n);
   if (b->prec == IEDG_F64)
-    err = condense_launch_f64(b->proto64, (const CondenseArgs<double>*)b->d_segs, b->d_items, b->n_items, lw,
-                              stream);
+    err = condense_launch_f64(CondenseArgs<double>{}, (const CondenseArgs<double>*)b->d_segs, q, 0, stream);
   else if (b->prec == IEDG_BF16)
-    err = condense_launch_bf16(b->proto32, (const CondenseArgs<float>*)b->d_segs, b->d_items, b->n_items, lw,
-                               stream);
+    err = condense_launch_bf16(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, stream);
   else
-    err = condense_launch_f32(b->proto32, (const CondenseArgs<float>*)b->d_segs, b->d_items, b->n_items, lw,
-                              stream);
+    err = condense_launch_f32(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, stream);
   if (err != hipSuccess) return hip_check(ctx, err, "condense_batched launch");
   return IEDG_OK;
 }
@@ -264,6 +294,7 @@ extern "C" void iedg_batch_destroy(iedg_batch b) {
   if (!b) return;
   if (b->d_segs) hipFree(b->d_segs);
   if (b->d_items) hipFree(b->d_items);
+  if (b->d_counter) hipFree(b->d_counter);
   delete b;
 }
 

@@ -3,9 +3,11 @@
 
 namespace iedg {
 
-hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const int2* items,
-                                int n_items, int lw, hipStream_t s) {
-  return dispatch_condense<float, 1>(a, s, lw, segs, items, n_items);
+hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw,
+                                hipStream_t s) {
+  return dispatch_condense<float, 1>(a, s, lw, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
 }
+
+int condense_queue_slots_bf16(int n_max) { return queue_slots<float, 1>(n_max); }
 
 }  // namespace iedg

@@ -3,9 +3,11 @@
 
 namespace iedg {
 
-hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const int2* items,
-                               int n_items, int lw, hipStream_t s) {
-  return dispatch_condense<float, 0>(a, s, lw, segs, items, n_items);
+hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw,
+                               hipStream_t s) {
+  return dispatch_condense<float, 0>(a, s, lw, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
 }
+
+int condense_queue_slots_f32(int n_max) { return queue_slots<float, 0>(n_max); }
 
 }  // namespace iedg

@@ -3,9 +3,11 @@
 
 namespace iedg {
 
-hipError_t condense_launch_f64(const CondenseArgs<double>& a, const CondenseArgs<double>* segs, const int2* items,
-                               int n_items, int lw, hipStream_t s) {
-  return dispatch_condense<double, 0>(a, s, lw, segs, items, n_items);
+hipError_t condense_launch_f64(const CondenseArgs<double>& a, const CondenseArgs<double>* segs, const QueueLaunch& q, int lw,
+                               hipStream_t s) {
+  return dispatch_condense<double, 0>(a, s, lw, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
 }
+
+int condense_queue_slots_f64(int n_max) { return queue_slots<double, 0>(n_max); }
 
 }  // namespace iedg

@@ -89,6 +89,7 @@ __device__ __attribute__((always_inline)) inline int wave_min(int v) {
 
 constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
+static_assert(NT == 512, "default_leaf_width counts rows per thread for 512 threads");
 constexpr int NW = NT / 64;   // waves
 constexpr int SWMAX = 16;     // widest sub-panel (LDS sizing)
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
@@ -1095,65 +1096,123 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   condense_one<T, QA, QC, LW, MM>(a, blockIdx.x, smem_raw);
 }
 
-// Batched form over a work list of (segment, element) items whose segments
-// share (n, t): one workgroup per item, all items in one launch.  A
-// workgroup holds one CU's LDS and register budget, so the dispatcher hands
-// the next item to whichever CU finishes first (uneven elements balance).
+// One item of the batched form, compiled as a function of its own so that
+// each size class gets its own register allocation (inlined together, the
+// six classes would share, and spill, one allocation).  A callee cannot know
+// that its arguments are uniform over the workgroup, so it makes them so
+// itself and reads the segment through the constant address space: the
+// segment's sizes and pointers then sit in scalar registers as they do in
+// the one-element-per-workgroup kernel.
 template <typename T, int QA, int QC, int LW, int MM>
-__global__ __launch_bounds__(NT) void condense_batched_kernel(const CondenseArgs<T>* segs, const int2* items) {
+__device__ __noinline__ void condense_item(const CondenseArgs<T>* segs, int seg, int e) {
+#if defined(__HIP_DEVICE_COMPILE__)  // address spaces exist only in the device pass
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int2 w = items[blockIdx.x];
-  const CondenseArgs<T> a = segs[w.x];
-  condense_one<T, QA, QC, LW, MM>(a, w.y, smem_raw);
+  typedef const __attribute__((address_space(4))) CondenseArgs<T> ConstArgs;
+  const uint64_t p = reinterpret_cast<uint64_t>(segs);
+  const uint64_t pu = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p) |
+                      ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(p >> 32)) << 32);
+  const CondenseArgs<T> a = ((ConstArgs*)pu)[__builtin_amdgcn_readfirstlane(seg)];
+  condense_one<T, QA, QC, LW, MM>(a, __builtin_amdgcn_readfirstlane(e), smem_raw);
+#endif
+}
+
+// Batched form, persistent: n_wg workgroups take (segment, element) items
+// from a queue (one atomic counter) until it runs dry.  Segments may differ
+// in element size: each item runs the instantiation of its size class and of
+// its segment's sub-panel width (a.lw), so it computes exactly what the
+// one-element-per-workgroup kernel computes for it (bitwise).  The work list
+// is ordered largest elements first, so the last items taken are short ones.
+template <typename T, int MM>
+__global__ __launch_bounds__(NT) void condense_queue_kernel(const CondenseArgs<T>* __restrict__ segs,
+                                                            const int2* __restrict__ items, int n_items,
+                                                            int* counter) {
+  __shared__ int next;
+  while (true) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    // the item index, and so the segment's sizes and pointers, are uniform
+    // over the workgroup: keep them in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();  // every thread has read `next` before thread 0 overwrites it
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const int seg = __builtin_amdgcn_readfirstlane(w.x), e = __builtin_amdgcn_readfirstlane(w.y);
+    const int n = segs[seg].n, t = segs[seg].t, lw = segs[seg].lw;
+    const int qa = (n + NT - 1) / NT, qc = (t + NT - 1) / NT;
+    if (qa <= 1 && qc <= 1) {
+      if (lw == 16) condense_item<T, 1, 1, 16, MM>(segs, seg, e);
+      else condense_item<T, 1, 1, 8, MM>(segs, seg, e);
+    } else if (qa <= 3 && qc <= 1) {
+      if (lw == 16) condense_item<T, 3, 1, 16, MM>(segs, seg, e);
+      else condense_item<T, 3, 1, 8, MM>(segs, seg, e);
+    } else {
+      if (lw == 16) condense_item<T, 5, 2, 16, MM>(segs, seg, e);
+      else condense_item<T, 5, 2, 8, MM>(segs, seg, e);
+    }
+  }
+}
+
+// Resets the queue counter on the stream (a kernel, not a memset, so that the
+// pair can be captured in a graph).  A template only so that the precision
+// translation units may each instantiate it.
+template <typename T>
+__global__ void condense_queue_reset_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
 template <typename T, int QA, int QC, int LW, int MM>
-hipError_t launch_condense_lw(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
-                              int n_items, hipStream_t s) {
+hipError_t launch_condense_lw(const CondenseArgs<T>& a, hipStream_t s) {
   const size_t smem = CondenseSmem<T>::bytes(a.n);
-  if (!segs) {
-    auto kern = condense_kernel<T, QA, QC, LW, MM>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
-  } else {
-    auto kern = condense_batched_kernel<T, QA, QC, LW, MM>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_items), dim3(NT), smem, s, segs, items);
-  }
+  auto kern = condense_kernel<T, QA, QC, LW, MM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(a.E), dim3(NT), smem, s, a);
   return hipGetLastError();
 }
 
-// Untuned sub-panel width: 16 where (QA + QC) x 16 register values stay
-// within the register file without spilling (FP32 up to 4 rows per thread,
-// FP64 up to 2), else 8.
-template <typename T>
-inline int default_leaf_width(int n, int t) {
-  const int qa = (n + NT - 1) / NT, qc = (t + NT - 1) / NT;
-  const int q = (qa <= 1 && qc <= 1) ? 2 : (qa <= 3 && qc <= 1) ? 4 : 7;
-  return (sizeof(T) == 8 ? q <= 2 : q <= 4) ? 16 : 8;
+template <typename T, int QA, int QC, int MM>
+hipError_t launch_condense(const CondenseArgs<T>& a, int lw, hipStream_t s) {
+  if (lw == 16) return launch_condense_lw<T, QA, QC, 16, MM>(a, s);
+  return launch_condense_lw<T, QA, QC, 8, MM>(a, s);
 }
 
-template <typename T, int QA, int QC, int MM>
-hipError_t launch_condense(const CondenseArgs<T>& a, const CondenseArgs<T>* segs, const int2* items,
-                           int n_items, int lw, hipStream_t s) {
-  if (lw == 16) return launch_condense_lw<T, QA, QC, 16, MM>(a, segs, items, n_items, s);
-  return launch_condense_lw<T, QA, QC, 8, MM>(a, segs, items, n_items, s);
+// Workgroups of the batched form that fit on the device at once (the
+// persistent grid) when LDS is sized for n_max local dofs.
+template <typename T, int MM>
+int queue_slots(int n_max) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t smem = CondenseSmem<T>::bytes(n_max);
+  auto kern = condense_queue_kernel<T, MM>;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)smem) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, smem) != hipSuccess) return 0;
+  return cus * per_cu;
 }
 
 // Every instantiation of one precision (and operand mode); each precision
 // is compiled in a translation unit of its own.
 template <typename T, int MM>
 hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, const CondenseArgs<T>* segs,
-                             const int2* items, int n_items) {
+                             const int2* items, int n_items, int n_max, int* counter, int n_wg) {
+  if (segs) {
+    const size_t smem = CondenseSmem<T>::bytes(n_max);
+    auto kern = condense_queue_kernel<T, MM>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(condense_queue_reset_kernel<T>, dim3(1), dim3(64), 0, s, counter);
+    hipLaunchKernelGGL(kern, dim3(n_wg), dim3(NT), smem, s, segs, items, n_items, counter);
+    return hipGetLastError();
+  }
   const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
-  if (lw == 0) lw = default_leaf_width<T>(a.n, a.t);
-  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1, MM>(a, segs, items, n_items, lw, s);
-  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1, MM>(a, segs, items, n_items, lw, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, MM>(a, segs, items, n_items, lw, s);
+  if (lw == 0) lw = default_leaf_width(sizeof(T), a.n, a.t);
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1, MM>(a, lw, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1, MM>(a, lw, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, MM>(a, lw, s);
   return hipErrorInvalidValue;
 }
 

@@ -95,26 +95,41 @@ def test_gmres_enqueue_equals_host_cycle(ctx, prec, dims, p):
 
 
 def test_batched_condense_equals_single_launch(ctx):
+    """One persistent launch over meshes of four element sizes computes what
+    one launch per mesh computes, bitwise; a second run (the queue counter
+    reset on the stream) again; a segment without elements is skipped."""
     from paper_1605_01020_amd.batch import Simulation
+    from paper_1605_01020_amd import F32
     _say("batched condensation vs per-mesh condensation")
     sims = [Simulation(ctx, c, SEED) for c in CASES]
     for s in sims:
         s.generate()
-    plans = {}
-    for s in sims:
-        plans.setdefault(s.n, []).append(s)
-    for n, group in plans.items():
-        pl = api.CondenseBatch(ctx, [s.condense_segment() for s in group], prec=s.prec)
-        pl.run()
-        torch.cuda.synchronize()
-        ctx.sync_status()
-        for s in group:
+    # a non-default sub-panel width for p = 2: the plan takes the context's
+    # width per size, as iedg_condense does
+    n_p2 = next(s.n for s in sims if s.case.p == 2)
+    api.set_leaf_width(ctx, n_p2, 8, prec=F32)
+    try:
+        empty = {k: v[:0] for k, v in sims[0].inp.items() if v is not None}
+        empty_out = {k: v[:0] for k, v in sims[0].fac.items()}
+        pl = api.CondenseBatch(ctx, [s.condense_segment() for s in sims] + [(empty, empty_out)], prec=sims[0].prec)
+        assert len(pl.sizes) == 4
+        refs = []
+        for s in sims:
             i = s.inp
-            ref = api.condense(ctx, i["A"], i["B"], i["C"], i["D"], i["F"], prec=s.prec)
+            refs.append(api.condense(ctx, i["A"], i["B"], i["C"], i["D"], i["F"], prec=s.prec))
+        for rep in range(2):
+            for s in sims:
+                for k in ("Ke", "r", "LU"):
+                    s.fac[k].fill_(float("nan"))
+            pl.run()
             torch.cuda.synchronize()
-            for k in ("LU", "perm", "U12", "L21", "Ke", "w", "r"):
-                assert torch.equal(ref[k], s.fac[k]), (s.case, k)
+            ctx.sync_status()
+            for s, ref in zip(sims, refs):
+                for k in ("LU", "perm", "U12", "L21", "Ke", "w", "r"):
+                    assert torch.equal(ref[k], s.fac[k]), (rep, s.case, k)
         pl.close()
+    finally:
+        api.set_leaf_width(ctx, n_p2, 16, prec=F32)
     for s in sims:
         s.close()
 

@@ -2,6 +2,8 @@
 // eq. LS), BILU(0) factorisation and its triangular sweeps, and the BSR
 // matrix-vector product (section 2.2.2).  Blocks are b x b, column-major,
 // stored in the row order of the mesh's ordering (see iedg.h).
+#include <cfloat>
+
 #include "blockops.h"
 #include "common.h"
 #include "mesh.h"
@@ -174,194 +176,304 @@ __global__ __launch_bounds__(STHR) void sweep_kernel(int b, const int32_t* rows,
 }
 
 // ---- BILU(0) factorisation ------------------------------------------------
-// One level of BILU(0): one workgroup per block row i of the level.
+// One workgroup of FTHR threads per block row i of a level (section 2.2.2,
+// BILU(0)).  For each lower slot (i, k) in elimination order:
+//   L_ik = A_ik U_kk^{-1}          (A_ik staged row-major in LDS, the product
+//                                   written to LDS and to M),
+//   A_ij -= L_ik U_kj              (every j of the row coupled to k),
+// then the pivot block A_ii is inverted in place.  Block products are split
+// into strips of 16 columns: a wave forms one strip (all b rows) with 16x16x4
+// MFMA, its A fragments read from LDS as 4-vectors and its B fragments (4
+// consecutive k of one column of a column-major block) loaded from HBM as
+// vectors; the k index of the four MFMAs of a vector is permuted between
+// lanes, which reorders only the sum.  Strips of all updates of one slot are
+// dealt to the 8 waves.  The inversion is Gauss-Jordan with partial pivoting
+// in exchange form, the block held in registers (4 threads per row, CPT
+// columns each) with one workgroup barrier per column: each wave posts its
+// best candidate row to LDS, so after the barrier every thread knows the
+// pivot row without a second exchange.
+constexpr int FTHR = 512;
+
+template <typename T, int NB>
+struct FactorSmem {
+  static constexpr int lda = 16 * NB + 4;   // row stride of the row-major block (16-byte rows)
+  static constexpr int slot = 16 * NB;      // one posted candidate row
+  static constexpr size_t y_bytes = sizeof(T) * (size_t)(16 * NB) * lda;
+  static constexpr size_t slot_bytes = sizeof(T) * 2 * 8 * slot;
+  static constexpr size_t bytes = y_bytes + slot_bytes + 2 * 8 * sizeof(uint32_t) + 128 * sizeof(int);
+};
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef f4 type; };
+template <> struct Vec4<double> { typedef d4 type; };
+
+// Row of the A fragment supplied by lane li so that the accumulator lane
+// (li, lg) holds rows 4 lg .. 4 lg + 3 of its column (FP64 MFMA lays its
+// output rows out as lg + 4 v).
 template <typename T>
-__global__ __launch_bounds__(STHR) void ilu0_level_kernel(int b, const int32_t* rows, const int32_t* diag_slot,
-                                                          const int32_t* lptr, const int32_t* lslot,
-                                                          const int32_t* uptr, const int32_t* upd, T* M,
-                                                          DeviceStatus* status) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* a = reinterpret_cast<T*>(smem_raw);                        // b x (b+1)
-  int* piv = reinterpret_cast<int*>(a + (size_t)b * (b + 1));   // b
-  double* rv = reinterpret_cast<double*>(piv + 128);            // 1
-  int* ri = reinterpret_cast<int*>(rv + 1);                     // 1
-  const int i = rows[blockIdx.x];
-  const size_t bb = (size_t)b * b;
-  for (int l = lptr[i]; l < lptr[i + 1]; ++l) {
-    const int sik = lslot[2 * l], dk = lslot[2 * l + 1];
-    // L_ik = A_ik * Uinv_k
-    block_mm<T>(b, M + sik * bb, M + dk * bb, M + sik * bb, 0);
-    sync_global();
-    for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
-      const int skj = upd[2 * u], sij = upd[2 * u + 1];
-      block_mm<T>(b, M + sik * bb, M + skj * bb, M + sij * bb, 1);
-    }
-    sync_global();
-  }
-  // pivot block: invert in place
-  T* D = M + diag_slot[i] * bb;
-  for (int q = threadIdx.x; q < b * b; q += STHR) {
-    const int c = q / b, r = q % b;
-    a[r * (b + 1) + c] = D[q];
-  }
-  __syncthreads();
-  const bool ok = gj_invert<T>(a, b, piv, rv, ri);
-  if (!ok && threadIdx.x == 0) latch_status(status, IEDG_ERR_SINGULAR, i);
-  for (int q = threadIdx.x; q < b * b; q += STHR) {
-    const int c = q / b, r = q % b;
-    D[q] = a[r * (b + 1) + c];
-  }
+__device__ __forceinline__ int frag_row(int li) {
+  return sizeof(T) == 8 ? 4 * (li & 3) + (li >> 2) : li;
 }
 
-// One level of BILU(0) with both operands of every block product staged in
-// LDS (b x b blocks, column-major, stride b + 1): sX holds A_ik and then
-// L_ik = A_ik U_kk^{-1}; sB holds the right operand (U_kk^{-1}, then each
-// U_kj).  Products run on MFMA with 16 x 16 tiles dealt round-robin to the
-// four waves; A_ij -= L_ik U_kj is applied tile by tile to global memory.
-// Copy up to two b x b blocks from global to LDS (stride b + 1), 8 loads in
-// flight per thread per block.
-template <typename T>
-__device__ inline void lds_block_load2(const T* g0, T* s0, const T* g1, T* s1, int b) {
-  const int ls = b + 1, bb = b * b;
-  for (int q0 = threadIdx.x; q0 < bb; q0 += STHR * 8) {
-    T v0[8], v1[8];
+// Y[r * lda + c] = G[c * b + r] for r, c < b (a column-major block to
+// row-major LDS), 4 loads in flight per thread.
+template <typename T, int NB>
+__device__ __forceinline__ void stage_rowmajor(const T* __restrict__ G, T* Y, int b) {
+  constexpr int lda = FactorSmem<T, NB>::lda;
+  const int bb = b * b;
+  for (int q0 = threadIdx.x; q0 < bb; q0 += FTHR * 4) {
+    T v[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int q = q0 + STHR * j;
-      v0[j] = q < bb ? g0[q] : T(0);
-      v1[j] = (g1 && q < bb) ? g1[q] : T(0);
+    for (int j = 0; j < 4; ++j) {
+      const int q = q0 + FTHR * j;
+      v[j] = q < bb ? G[q] : T(0);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int q = q0 + STHR * j;
+    for (int j = 0; j < 4; ++j) {
+      const int q = q0 + FTHR * j;
       if (q < bb) {
-        const int c = q / b, r = q % b;
-        s0[c * ls + r] = v0[j];
-        if (g1) s1[c * ls + r] = v1[j];
+        const int c = q / b, r = q - c * b;
+        Y[r * lda + c] = v[j];
       }
     }
   }
 }
 
-template <typename T>
-__device__ inline void lds_block_mm(int b, const T* sA, const T* sB, typename Mfma<T>::acc_t (&acc)[16]) {
-  typedef Mfma<T> MF;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int nt = (b + 15) / 16, ntiles = nt * nt, ls = b + 1;
+// B fragment of chunk c: B[16 c + 4 lg + s][j], s = 0..3 (zero past b).
+template <typename T, bool VEC>
+__device__ __forceinline__ typename Vec4<T>::type load_bfrag(const T* __restrict__ B, int b, int j, int k0) {
+  typedef typename Vec4<T>::type V4;
+  V4 x = V4{T(0), T(0), T(0), T(0)};
+  if constexpr (VEC) {
+    if (j < b && k0 < b) x = *reinterpret_cast<const V4*>(B + (size_t)j * b + k0);
+  } else {
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    acc[q] = MF::zero();
-    const int tI = wv + 4 * q;
-    if (tI < ntiles) {
-      const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
-      const int ia = i0 + li, jb = j0 + li;
-      for (int k0 = 0; k0 < b; k0 += 4) {
-        const int k = k0 + lg;
-        const T av = (ia < b && k < b) ? sA[k * ls + ia] : T(0);
-        const T bv = (jb < b && k < b) ? sB[jb * ls + k] : T(0);
-        acc[q] = MF::mac(av, bv, acc[q]);
+    for (int s = 0; s < 4; ++s)
+      if (j < b && k0 + s < b) x[s] = B[(size_t)j * b + k0 + s];
+  }
+  return x;
+}
+
+// acc[q] = (Y B)[16 q .. 16 q + 15, j0 .. j0 + 15] for q < NB: Y row-major in
+// LDS (rows and columns past b zero), B a column-major b x b block in HBM.
+// The next chunk's B fragment is loaded while the current one is consumed;
+// tile rows are taken in pairs so that consecutive MFMAs are independent.
+template <typename T, int NB, bool VEC>
+__device__ __forceinline__ void strip_mm(const T* Y, const T* __restrict__ B, int b, int j0,
+                                         typename Mfma<T>::acc_t (&acc)[NB]) {
+  typedef Mfma<T> MF;
+  typedef typename Vec4<T>::type V4;
+  constexpr int lda = FactorSmem<T, NB>::lda;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int j = j0 + li;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) acc[q] = MF::zero();
+  const T* yrow = Y + frag_row<T>(li) * lda + 4 * lg;
+  V4 bn = load_bfrag<T, VEC>(B, b, j, 4 * lg);
+  // a rolled chunk loop keeps one chunk's A fragments live (unrolled, the
+  // scheduler hoists every chunk's LDS reads and runs out of registers)
+#pragma unroll 1
+  for (int c = 0; c < NB; ++c) {
+    const V4 bc = bn;
+    if (c + 1 < NB) bn = load_bfrag<T, VEC>(B, b, j, 16 * (c + 1) + 4 * lg);
+#pragma unroll
+    for (int q = 0; q < NB; q += 2) {
+      const V4 a0 = *reinterpret_cast<const V4*>(yrow + 16 * q * lda + 16 * c);
+      if (q + 1 < NB) {
+        const V4 a1 = *reinterpret_cast<const V4*>(yrow + 16 * (q + 1) * lda + 16 * c);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc[q] = MF::mac(a0[s], bc[s], acc[q]);
+          acc[q + 1] = MF::mac(a1[s], bc[s], acc[q + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc[q] = MF::mac(a0[s], bc[s], acc[q]);
       }
     }
   }
 }
 
-// STAGE_C: the block being updated is staged in LDS too (three b x b buffers);
-// otherwise (large b) the update is applied to it in global memory in the
-// accumulator layout and two buffers suffice.
-template <typename T, bool STAGE_C>
-__global__ __launch_bounds__(STHR) void ilu0_level_lds_kernel(int b, const int32_t* rows, const int32_t* diag_slot,
-                                                              const int32_t* lptr, const int32_t* lslot,
-                                                              const int32_t* uptr, const int32_t* upd, T* M,
-                                                              DeviceStatus* status) {
+// C = acc (sub false) or C -= acc (sub true) on the accumulator rows
+// 16 q + 4 lg .. + 3 of column j0 + li (rows and columns past b skipped).
+template <typename T, int NB, bool VEC>
+__device__ __forceinline__ void strip_rmw(T* C, int b, int j0, const typename Mfma<T>::acc_t (&acc)[NB], bool sub) {
+  typedef typename Vec4<T>::type V4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  const int j = j0 + li;
+  if (j >= b) return;
+  T* col = C + (size_t)j * b;
+  if constexpr (VEC) {
+    V4 x[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int i0 = 16 * q + 4 * lg;
+      if (sub && i0 < b) x[q] = *reinterpret_cast<const V4*>(col + i0);
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int i0 = 16 * q + 4 * lg;
+      if (i0 < b) {
+        V4 y;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[v] = sub ? x[q][v] - acc[q][v] : acc[q][v];
+        *reinterpret_cast<V4*>(col + i0) = y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * q + 4 * lg + v;
+        if (i < b) col[i] = sub ? col[i] - acc[q][v] : acc[q][v];
+      }
+  }
+}
+
+template <typename T, int NB, bool VEC>
+__global__ __launch_bounds__(FTHR) void ilu0_row_kernel(int b, const int32_t* __restrict__ rows,
+                                                        const int32_t* __restrict__ diag_slot,
+                                                        const int32_t* __restrict__ lptr,
+                                                        const int32_t* __restrict__ lslot,
+                                                        const int32_t* __restrict__ uptr,
+                                                        const int32_t* __restrict__ upd, T* M,
+                                                        DeviceStatus* status) {
   typedef Mfma<T> MF;
+  typedef FactorSmem<T, NB> SM;
+  typedef typename Vec4<T>::type V4;
+  constexpr int lda = SM::lda, CPT = 4 * NB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ls = b + 1;
-  T* sX = reinterpret_cast<T*>(smem_raw);   // b x ls: A_ik, then L_ik
-  T* sB = sX + (size_t)b * ls;              // b x ls: right operand
-  T* sC = sB + (size_t)b * ls;              // b x ls: block being updated (STAGE_C)
-  int* piv = reinterpret_cast<int*>(STAGE_C ? sC + (size_t)b * ls : sC);
-  double* rv = reinterpret_cast<double*>(piv + 128);
-  int* ri = reinterpret_cast<int*>(rv + 1);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, li = lane & 15;
-  const int nt = (b + 15) / 16, ntiles = nt * nt;
+  T* Y = reinterpret_cast<T*>(smem_raw);
+  T* slots = reinterpret_cast<T*>(smem_raw + SM::y_bytes);                   // [2][8][16 NB]
+  uint32_t* skey = reinterpret_cast<uint32_t*>(smem_raw + SM::y_bytes + SM::slot_bytes);  // [2][8]
+  int* prow = reinterpret_cast<int*>(skey + 16);                                         // [128]
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int i = rows[blockIdx.x];
   const size_t bb = (size_t)b * b;
-  typename MF::acc_t acc[16];
+  // rows and columns of Y past b stay zero (finite operands where k >= b)
+  for (int q = tid; q < 16 * NB * lda; q += FTHR) Y[q] = T(0);
+  __syncthreads();
+  typename MF::acc_t acc[NB];
   for (int l = lptr[i]; l < lptr[i + 1]; ++l) {
     const int sik = lslot[2 * l], dk = lslot[2 * l + 1];
-    lds_block_load2<T>(M + sik * bb, sX, M + dk * bb, sB, b);
+    T* Aik = M + (size_t)sik * bb;
+    stage_rowmajor<T, NB>(Aik, Y, b);
     __syncthreads();
-    lds_block_mm<T>(b, sX, sB, acc);
-    __syncthreads();
-    // L_ik into sX (LDS), then to M[sik] from LDS (coalesced)
+    if (wv < NB) strip_mm<T, NB, VEC>(Y, M + (size_t)dk * bb, b, 16 * wv, acc);
+    __syncthreads();  // every wave has read A_ik from Y
+    if (wv < NB) {
+      strip_rmw<T, NB, VEC>(Aik, b, 16 * wv, acc, false);
+      const int li = lane & 15, lg = lane >> 4, j = 16 * wv + li;
+      if (j < b)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int tI = wv + 4 * q;
-      if (tI < ntiles) {
-        const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = i0 + MF::row(lane, v), c = j0 + li;
-          if (r < b && c < b) sX[c * ls + r] = acc[q][v];
-        }
-      }
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < (int)bb; q += STHR) M[sik * bb + q] = sX[(q / b) * ls + q % b];
-    for (int u = uptr[l]; u < uptr[l + 1]; ++u) {
-      const int skj = upd[2 * u], sij = upd[2 * u + 1];
-      T* C = M + sij * bb;
-      if constexpr (STAGE_C) {
-        lds_block_load2<T>(M + skj * bb, sB, C, sC, b);
-      } else {
-        lds_block_load2<T>(M + skj * bb, sB, nullptr, nullptr, b);
-      }
-      __syncthreads();
-      lds_block_mm<T>(b, sX, sB, acc);
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int tI = wv + 4 * q;
-        if (tI < ntiles) {
-          const int i0 = (tI / nt) * 16, j0 = (tI % nt) * 16;
+        for (int q = 0; q < NB; ++q)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int r = i0 + MF::row(lane, v), c = j0 + li;
-            if (r < b && c < b) {
-              if constexpr (STAGE_C)
-                sC[c * ls + r] -= acc[q][v];
-              else
-                C[(size_t)c * b + r] -= acc[q][v];
-            }
+            const int r = 16 * q + 4 * lg + v;
+            if (r < b) Y[r * lda + j] = acc[q][v];
           }
+    }
+    __syncthreads();  // L_ik in Y
+    const int u0 = uptr[l], nu = uptr[l + 1] - u0;
+    for (int w = wv; w < nu * NB; w += FTHR / 64) {
+      const int u = u0 + w / NB, c = w - (w / NB) * NB;
+      strip_mm<T, NB, VEC>(Y, M + (size_t)upd[2 * u] * bb, b, 16 * c, acc);
+      strip_rmw<T, NB, VEC>(M + (size_t)upd[2 * u + 1] * bb, b, 16 * c, acc, true);
+    }
+    sync_global();  // the next slot reads blocks other waves updated
+  }
+  // ---- pivot block: Gauss-Jordan inverse in exchange form ----
+  T* Dg = M + (size_t)diag_slot[i] * bb;
+  stage_rowmajor<T, NB>(Dg, Y, b);
+  __syncthreads();
+  const int r = tid >> 2, h = tid & 3;  // row r, columns h CPT .. h CPT + CPT - 1
+  const bool live = r < b;
+  T W[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; j += 4) {
+    V4 x = V4{T(0), T(0), T(0), T(0)};
+    if (r < 16 * NB) x = *reinterpret_cast<const V4*>(Y + r * lda + h * CPT + j);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) W[j + s] = x[s];
+  }
+  bool pivoted = false, ok = true;
+  int mystep = -1;
+  // Waves past the last row (b <= 16 NB rows, 16 rows a wave) only keep the
+  // barriers.  A candidate's key is its magnitude in FP32 with the low 8
+  // mantissa bits replaced by 255 - row (never zero, which marks "no
+  // candidate"): the largest key is the largest magnitude to 2^-15
+  // relative, ties to the smaller row (the pivot must only
+  // be near the column maximum for stability, and equal keys give the same
+  // choice on every run).  NaN and Inf are taken first, and flagged.
+  const bool active = wv < NB;
+  for (int hk = 0; hk < 4; ++hk) {
+#pragma unroll
+    for (int kk = 0; kk < CPT; ++kk) {
+      const int k = hk * CPT + kk;
+      if (k < b) {
+        const int par = k & 1;
+        T v = T(0);
+        if (active) {
+          v = __shfl(W[kk], (lane & ~3) | hk, kWave);  // entry (r, k)
+          float fm = fabsf((float)v);
+          if (!(fm <= FLT_MAX)) fm = INFINITY;
+          uint32_t key = (live && !pivoted) ? ((__float_as_uint(fm) & ~255u) | (uint32_t)(255 - r)) : 0u;
+#pragma unroll
+          for (int off = 4; off < 64; off <<= 1) key = max(key, (uint32_t)__shfl_xor((int)key, off, kWave));
+          if (key != 0u && r == 255 - (int)(key & 255u)) {
+            T* sl = slots + (par * 8 + wv) * SM::slot + h * CPT;
+#pragma unroll
+            for (int j = 0; j < CPT; j += 4) *reinterpret_cast<V4*>(sl + j) = V4{W[j], W[j + 1], W[j + 2], W[j + 3]};
+          }
+          if (lane == 0) skey[par * 8 + wv] = key;
+        }
+        __syncthreads();
+        if (active) {
+          uint32_t best = skey[par * 8];
+#pragma unroll
+          for (int w = 1; w < NB; ++w) best = max(best, skey[par * 8 + w]);
+          const int p = 255 - (int)(best & 255u);
+          const T* ps = slots + (par * 8 + (p >> 4)) * SM::slot;
+          const T piv = ps[k];
+          if (!(piv != T(0)) || !(fabs((double)piv) <= DBL_MAX)) ok = false;
+          const T ip = T(1) / piv;
+          const T c = -(v * ip);
+          // every row: W(r, c') -= W(r, k) W(p, c') / W(p, k)
+#pragma unroll
+          for (int j = 0; j < CPT; j += 4) {
+            const V4 x = *reinterpret_cast<const V4*>(ps + h * CPT + j);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) W[j + s] = fma(c, x[s], W[j + s]);
+          }
+          const bool me = r == p;
+          if (me) {  // the pivot row: W(p, c') = -W(p, c') / W(p, k)
+#pragma unroll
+            for (int j = 0; j < CPT; j += 4) {
+              const V4 x = *reinterpret_cast<const V4*>(ps + h * CPT + j);
+#pragma unroll
+              for (int s = 0; s < 4; ++s) W[j + s] = -(x[s] * ip);
+            }
+            pivoted = true;
+            mystep = k;
+          }
+          if (h == hk) W[kk] = me ? ip : v * ip;  // column k: 1 / W(p, k) and W(r, k) / W(p, k)
+          if (tid == 0) prow[k] = p;
         }
       }
-      if constexpr (STAGE_C) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < (int)bb; q += STHR) C[q] = sC[(q / b) * ls + q % b];
-        __syncthreads();
-      } else {
-        sync_global();  // sB is reloaded next; C may be updated again
-      }
     }
-    sync_global();
   }
-  // pivot block: invert in place (row-major staging in sX)
-  T* Dg = M + diag_slot[i] * bb;
-  T* sD = STAGE_C ? sC : sB;
-  lds_block_load2<T>(Dg, sD, nullptr, nullptr, b);
+  __syncthreads();  // prow complete; Y no longer read
+  // inverse(step(r), prow[c]) = W(r, c), staged column-major in Y
+  if (live && mystep >= 0)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int c = h * CPT + j;
+      if (c < b) Y[prow[c] * b + mystep] = W[j];
+    }
   __syncthreads();
-  for (int q = threadIdx.x; q < (int)bb; q += STHR) {
-    const int c = q / b, r = q % b;
-    sX[r * ls + c] = sD[c * ls + r];
-  }
-  __syncthreads();
-  const bool ok = gj_invert<T>(sX, b, piv, rv, ri);
-  if (!ok && threadIdx.x == 0) latch_status(status, IEDG_ERR_SINGULAR, i);
-  for (int q = threadIdx.x; q < (int)bb; q += STHR) {
-    const int c = q / b, r = q % b;
-    Dg[q] = sX[r * ls + c];
-  }
+  for (int q = tid; q < (int)bb; q += FTHR) Dg[q] = Y[q];
+  if (!ok && tid == 0) latch_status(status, IEDG_ERR_SINGULAR, i);
 }
 
 template <typename T>
@@ -411,6 +523,37 @@ iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, co
 
 }  // namespace iedg
 
+template <typename T, int NB>
+static iedg_status factor_levels_nb(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
+  const size_t smem = FactorSmem<T, NB>::bytes;
+  auto kern = (m->b % 4 == 0) ? ilu0_row_kernel<T, NB, true> : ilu0_row_kernel<T, NB, false>;
+  IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem));
+  for (int l = 0; l < m->n_levels; ++l) {
+    const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(kern, dim3(cnt), dim3(FTHR), smem, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
+                       m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, M, ctx->d_status);
+    IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
+  }
+  return IEDG_OK;
+}
+
+template <typename T>
+static iedg_status factor_levels(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
+  switch ((m->b + 15) / 16) {
+    case 1: return factor_levels_nb<T, 1>(ctx, m, M, stream);
+    case 2: return factor_levels_nb<T, 2>(ctx, m, M, stream);
+    case 3: return factor_levels_nb<T, 3>(ctx, m, M, stream);
+    case 4: return factor_levels_nb<T, 4>(ctx, m, M, stream);
+    case 5: return factor_levels_nb<T, 5>(ctx, m, M, stream);
+    case 6: return factor_levels_nb<T, 6>(ctx, m, M, stream);
+    case 7: return factor_levels_nb<T, 7>(ctx, m, M, stream);
+    case 8: return factor_levels_nb<T, 8>(ctx, m, M, stream);
+  }
+  return set_error(ctx, IEDG_ERR_UNSUPPORTED, "factor_ilu0: b=%d", m->b);
+}
+
 extern "C" {
 
 iedg_status iedg_assemble(iedg_context ctx, iedg_mesh m, iedg_prec prec, const void* Ke, const double* r,
@@ -447,49 +590,13 @@ iedg_status iedg_assemble(iedg_context ctx, iedg_mesh m, iedg_prec prec, const v
 iedg_status iedg_factor_ilu0(iedg_context ctx, iedg_mesh m, iedg_prec prec, const void* Kbsr, void* Mbsr,
                              hipStream_t stream) {
   if (!ctx || !m || !Kbsr || !Mbsr) return IEDG_ERR_INVALID_ARG;
+  if (prec != IEDG_F64 && prec != IEDG_F32 && prec != IEDG_BF16)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "factor_ilu0: precision");
   const size_t es = prec_size(prec);
   if (Kbsr != Mbsr)
     IEDG_HIP(ctx, hipMemcpyAsync(Mbsr, Kbsr, es * m->nnzb * m->b * m->b, hipMemcpyDeviceToDevice, stream));
-  const size_t smem = es * m->b * (m->b + 1) + sizeof(int) * 128 + 2 * sizeof(double);
-  const size_t tail = sizeof(int) * 128 + 2 * sizeof(double);
-  const size_t smem3 = 3 * es * m->b * (m->b + 1) + tail, smem2 = 2 * es * m->b * (m->b + 1) + tail;
-  const int mode = smem3 <= 160 * 1024 ? 3 : (smem2 <= 160 * 1024 ? 2 : 0);
-  for (int l = 0; l < m->n_levels; ++l) {
-    const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
-    if (mode) {
-      const size_t sm = mode == 3 ? smem3 : smem2;
-      auto launch = [&](auto kern, auto* Mp) -> iedg_status {
-        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
-        hipLaunchKernelGGL(kern, dim3(cnt), dim3(STHR), sm, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
-                           m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, Mp, ctx->d_status);
-        return IEDG_OK;
-      };
-      iedg_status st;
-      if (prec == IEDG_F64)
-        st = mode == 3 ? launch(ilu0_level_lds_kernel<double, true>, (double*)Mbsr)
-                       : launch(ilu0_level_lds_kernel<double, false>, (double*)Mbsr);
-      else
-        st = mode == 3 ? launch(ilu0_level_lds_kernel<float, true>, (float*)Mbsr)
-                       : launch(ilu0_level_lds_kernel<float, false>, (float*)Mbsr);
-      if (st != IEDG_OK) return st;
-      IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
-      continue;
-    }
-    if (prec == IEDG_F64) {
-      auto k = ilu0_level_kernel<double>;
-      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
-                         m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (double*)Mbsr, ctx->d_status);
-    } else {
-      auto k = ilu0_level_kernel<float>;
-      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      hipLaunchKernelGGL(k, dim3(cnt), dim3(STHR), smem, stream, m->b, m->d_level_rows + r0, m->d_diag_slot,
-                         m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, (float*)Mbsr, ctx->d_status);
-    }
-    IEDG_LAUNCH_CHECK(ctx, "ilu0 level launch");
-  }
-  return IEDG_OK;
+  if (prec == IEDG_F64) return factor_levels<double>(ctx, m, (double*)Mbsr, stream);
+  return factor_levels<float>(ctx, m, (float*)Mbsr, stream);
 }
 
 iedg_status iedg_spmv(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const void* K, const double* x, double* y,

@@ -371,27 +371,7 @@ def test_config0_mixed_bf16_refinement(ctx, cfg0_oracle):
     assert rel(z.cpu().numpy(), np.stack(ref["z"])) <= 1e-7
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_ilu0_large_blocks(ctx, prec):
-    """b = 125 (p = 4): FP32 blocks use the two-buffer LDS kernel (the block
-    being updated stays in global memory), FP64 blocks the unstaged kernel.
-    Tolerances: FP64 as above; FP32 blocks 2e-5 relative (unit roundoff 6e-8
-    over chains of block products of order 125)."""
-    m, spec, blocks, G = host_case((2, 1, 1), 4)
-    tm = _tmesh(m, spec)
-    mesh = _mesh(ctx, m, spec)
-    q = mesh.query()
-    Ks, rs = oracle.condense_all(blocks)
-    K, R = oracle.assemble(tm, Ks, rs, G)
-    _say(f"ilu0 b=125 prec={prec}")
-    Kd = dev(bsr_from_oracle(mesh, K, q))
-    if prec == 1:
-        Kd = Kd.float()
-    Md = api.factor_ilu0(ctx, mesh, Kd, prec=prec)
-    ctx.sync_status()
-    fac = oracle.bilu0(tm, K, q["order"])
-    got = oracle_from_bsr(mesh, Md.double().cpu().numpy(), q)
-    tol = 1e-11 if prec == 0 else 2e-5
+def _check_factors(got, fac, K, tol):
     scale = max(np.abs(v).max() for v in K.values())
     for key, Lb in fac["L"].items():
         assert np.abs(got[key] - Lb).max() <= tol * scale, key
@@ -400,6 +380,91 @@ def test_ilu0_large_blocks(ctx, prec):
             assert np.abs(got[key] - Ub).max() <= tol * scale, key
     for i, Ui in fac["Uinv"].items():
         assert np.abs(got[(i, i)] - Ui).max() <= tol * np.abs(Ui).max(), i
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ilu0_block_sizes(ctx, p, prec):
+    """Every face size of degrees 1 to 4 (b = 20, 45, 80, 125: 2 to 8 tiles
+    of 16, vector loads where b is a multiple of 4, scalar loads otherwise)
+    on a two-element mesh.  Tolerances: FP64 1e-11 of the largest entry of K
+    (of the pivot inverse for the diagonal blocks); FP32 blocks 2e-5 (unit
+    roundoff 6e-8 over chains of block products of order up to 125)."""
+    m, spec, blocks, G = host_case((2, 1, 1), p)
+    tm = _tmesh(m, spec)
+    mesh = _mesh(ctx, m, spec)
+    q = mesh.query()
+    Ks, rs = oracle.condense_all(blocks)
+    K, R = oracle.assemble(tm, Ks, rs, G)
+    _say(f"ilu0 b={spec.b} prec={prec}")
+    Kd = dev(bsr_from_oracle(mesh, K, q))
+    if prec == 1:
+        Kd = Kd.float()
+    Md = api.factor_ilu0(ctx, mesh, Kd, prec=prec)
+    ctx.sync_status()
+    fac = oracle.bilu0(tm, K, q["order"])
+    _check_factors(oracle_from_bsr(mesh, Md.double().cpu().numpy(), q), fac, K, 1e-11 if prec == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("b", [20, 45, 80, 125])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_ilu0_pivoting_permuted_blocks(ctx, b, prec):
+    """Pivot blocks P (4 I + N / (2 sqrt(b))) with P a random permutation:
+    their diagonal entries are small against the column maxima (down to 1e-6
+    of them), so the pivot inversions must interchange rows, while every
+    pivot stays well conditioned (condition number below 2) and the factors
+    are insensitive to roundoff (a relative perturbation of 2e-16 of K moves
+    them by about 1e-15).  Off-diagonal blocks N / sqrt(b).  Blocks compared
+    with the oracle relative to each block's largest entry: FP64 1e-12, FP32
+    (the oracle on the FP32-rounded K) 1e-5."""
+    hm = StructuredHexMesh(2, 2, 1)
+    tm = oracle.TraceMesh(hm.elem_faces(), hm.n_face, b)
+    rng = np.random.default_rng(b)
+    K = {}
+    for f in range(tm.n_face):
+        for g in tm.pattern[f]:
+            if f == g:
+                P = np.eye(b)[rng.permutation(b)]
+                K[(f, g)] = P @ (4 * np.eye(b) + 0.5 * rng.standard_normal((b, b)) / np.sqrt(b))
+            else:
+                K[(f, g)] = rng.standard_normal((b, b)) / np.sqrt(b)
+    if prec == 1:
+        K = {k: v.astype(np.float32).astype(np.float64) for k, v in K.items()}
+    mesh = api.Mesh(ctx, hm.elem_faces(), hm.n_face, b)
+    q = mesh.query()
+    _say(f"ilu0 permuted pivot blocks b={b} prec={prec}")
+    Kd = dev(bsr_from_oracle(mesh, K, q))
+    Md = api.factor_ilu0(ctx, mesh, Kd if prec == 0 else Kd.float(), prec=prec)
+    ctx.sync_status()
+    fac = oracle.bilu0(tm, K, q["order"])
+    got = oracle_from_bsr(mesh, Md.double().cpu().numpy(), q)
+    errs = {}
+    for key, blk in list(fac["L"].items()) + [(k, v) for k, v in fac["U"].items() if k[0] != k[1]]:
+        errs[key] = np.abs(got[key] - blk).max() / np.abs(blk).max()
+    for i, Ui in fac["Uinv"].items():
+        errs[(i, i)] = np.abs(got[(i, i)] - Ui).max() / np.abs(Ui).max()
+    worst = max(errs.values())
+    _say(f"  worst relative block error {worst:.2e}")
+    assert worst <= (1e-12 if prec == 0 else 1e-5)
+
+
+def test_ilu0_singular_pivot_block_reported(ctx):
+    """A zero pivot block latches IEDG_ERR_SINGULAR with its block row."""
+    hm = StructuredHexMesh(2, 1, 1)
+    b = 20
+    tm = oracle.TraceMesh(hm.elem_faces(), hm.n_face, b)
+    rng = np.random.default_rng(7)
+    K = {(f, g): rng.standard_normal((b, b)) + (8 * np.eye(b) if f == g else 0)
+         for f in range(tm.n_face) for g in tm.pattern[f]}
+    mesh = api.Mesh(ctx, hm.elem_faces(), hm.n_face, b, ordering="natural")
+    q = mesh.query()
+    first = int(q["order"][0])
+    K[(first, first)] = np.zeros((b, b))
+    api.factor_ilu0(ctx, mesh, dev(bsr_from_oracle(mesh, K, q)))
+    with pytest.raises(api.IedgError) as ei:
+        ctx.sync_status()
+    assert ei.value.status == -2 and ei.value.index == 0
+    ctx.sync_status()  # cleared
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])

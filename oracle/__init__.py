@@ -21,7 +21,10 @@ Galerkin method", section 2.2):
 * the restricted additive Schwarz preconditioner with delta-level overlap
   and BILU(0) subdomain solves (section 2.2.2), for N > 1 subdomains;
 * recovery of the element unknowns dZ_e = A_e^{-1} (F_e - B_e dU_e), which
-  the paper leaves implicit ("readily eliminated").
+  the paper leaves implicit ("readily eliminated");
+* the minimal-residual initial guess for Newton's method (section 2.2.1,
+  eq. MinRes2): Levenberg-Marquardt with finite-difference gradients over
+  combinations of previous solutions, on a synthetic nonlinear residual.
 
 Every function is written for clarity, not speed.  Parity status of each
 function is stated in its module docstring.
@@ -37,6 +40,7 @@ from .gmres import gmres
 from .backsolve import backsolve_element, backsolve_all
 from .residual import full_residual
 from .solve import newton_step_solve
+from .mr import mr_guess, nonlinear_residual
 
 __all__ = [
     "TraceMesh", "condense_element", "condense_all", "assemble",

@@ -372,6 +372,61 @@ iedg_status iedg_residual_full_noalloc(iedg_context ctx, iedg_mesh mesh, int32_t
 iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, const double* x,
                       double* y, hipStream_t stream);
 
+/* ---- f3: minimal-residual initial guess (section 2.2.1, eq. MinRes2) ---- */
+/* The Newton initial guess x0 = sum_j alpha_j x_j over s previous solutions
+ * x_j = (z_j, uhat_j), with alpha minimising ||R(x0)||^2 (both blocks of
+ * the residual), found by Levenberg-Marquardt with finite-difference
+ * gradients.  R is the residual of the uncondensed Newton system plus a
+ * componentwise cubic term (eps = 0: the linear residual of a6):
+ *   R_NS,e = F_e - A_e z_e - B_e uhat_e - eps z_e^3,
+ *   R_FL   = G - sum_e P_e^T (C_e z_e + D_e uhat_e) - eps uhat^3.
+ * Each evaluation pass reads the FP64 element blocks once for a batch of up
+ * to s_max + 1 points (a trial and its s finite-difference neighbours).
+ * Layouts: Zprev [s][E][n] and Uprev [s][N_t] FP64 device (previous
+ * solution j at index j, most recent first); A, B, C, D, F, G as for
+ * iedg_residual_full.
+ * iedg_mr_create allocates the state (two sets of s_max + 1 residual
+ * vectors of E n + N_t values, per-point partial sums, the Gram matrix and
+ * a pinned readback area); 1 <= s_max <= 8 (IEDG_ERR_UNSUPPORTED
+ * otherwise); the points of a pass must fit in LDS: (s + 1)(n + t) FP64
+ * values <= 160 KiB.
+ * iedg_mr_residual: R [m][E n + N_t] (device, element rows e-major then the
+ * trace) and sums [m] (device, ||R_k||^2) at the m <= s_max + 1 points
+ * point_k = sum_j beta[k s + j] x_j (beta host, [m][s]).  Launches only.
+ * iedg_mr_guess: alpha [s] (host), z0 [E][n] and u0 [N_t] (device) = the
+ * combination; synchronises `stream` after each pass and each Gram matrix
+ * (the s x s damped normal equations are solved on the host).  Algorithm
+ * (opts may be NULL: max_iters 20, lambda0 1e-3, fd_step 1e-7, tol 1e-10):
+ * start at alpha = e_1 and lambda0; Jacobian columns by forward differences
+ * with steps fd_step max(1, |alpha_i|); step (J^T J + lambda diag(J^T J)) d
+ * = -J^T r; accept if the objective decreases (lambda /= 10, floor 1e-12),
+ * else lambda *= 10 (at most 10 tries per step); stop after max_iters
+ * accepted steps, when no try is accepted, when max|d| <= tol (1 +
+ * max|alpha|), or at a zero objective.  info: accepted steps, passes, the
+ * objective at e_1 and at alpha. */
+typedef struct iedg_mr_s* iedg_mr;
+typedef struct {
+  int32_t max_iters;
+  double lambda0, fd_step, tol;
+} iedg_mr_opts;
+typedef struct {
+  int32_t iters, passes;
+  double obj0, obj;
+} iedg_mr_info;
+iedg_status iedg_mr_create(iedg_context ctx, iedg_mesh mesh, int32_t n_local, int32_t s_max,
+                           iedg_mr* out);
+void iedg_mr_destroy(iedg_mr mr);
+iedg_status iedg_mr_residual(iedg_context ctx, iedg_mr mr, const double* A, const double* B,
+                             const double* C, const double* D, const double* F, const double* G,
+                             double eps, int32_t s, const double* Zprev, const double* Uprev,
+                             int32_t m, const double* beta, double* R, double* sums,
+                             hipStream_t stream);
+iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr mr, const double* A, const double* B,
+                          const double* C, const double* D, const double* F, const double* G,
+                          double eps, int32_t s, const double* Zprev, const double* Uprev,
+                          const iedg_mr_opts* opts, double* alpha, double* z0, double* u0,
+                          iedg_mr_info* info, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

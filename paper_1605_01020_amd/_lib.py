@@ -34,6 +34,15 @@ class RasInfo(ctypes.Structure):
                 ("n_levels", c_int64)]
 
 
+class MrOpts(ctypes.Structure):
+    _fields_ = [("max_iters", c_int32), ("lambda0", ctypes.c_double), ("fd_step", ctypes.c_double),
+                ("tol", ctypes.c_double)]
+
+
+class MrInfo(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("passes", c_int32), ("obj0", ctypes.c_double), ("obj", ctypes.c_double)]
+
+
 class CondenseSegment(ctypes.Structure):
     _fields_ = [("n_elem", c_int32), ("A", P), ("B", P), ("C", P), ("D", P), ("F", P),
                 ("LU", P), ("perm", P), ("U12", P), ("L21", P), ("w", P), ("Ke", P), ("r", P)]
@@ -56,6 +65,11 @@ SIGNATURES = {
     "iedg_batch_create_sized": (c_int32, [P, c_int32, ctypes.POINTER(CondenseSegment), P, P,
                                           c_int32, ctypes.POINTER(c_void_p)]),
     "iedg_condense_batched": (c_int32, [P, P, P]),
+    "iedg_mr_create": (c_int32, [P, P, c_int32, c_int32, ctypes.POINTER(c_void_p)]),
+    "iedg_mr_destroy": (None, [P]),
+    "iedg_mr_residual": (c_int32, [P, P, P, P, P, P, P, P, ctypes.c_double, c_int32, P, P, c_int32, P, P, P, P]),
+    "iedg_mr_guess": (c_int32, [P, P, P, P, P, P, P, P, ctypes.c_double, c_int32, P, P, ctypes.POINTER(MrOpts), P,
+                                P, P, ctypes.POINTER(MrInfo), P]),
     "iedg_batch_destroy": (None, [P]),
     "iedg_set_leaf_width": (c_int32, [P, c_int32, c_int32, c_int32]),
     "iedg_condense_rhs": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P, P, P]),

@@ -389,3 +389,56 @@ def residual_full(ctx, mesh, A, B, C, D, F, G, z, uhat, rF=None, rG=None, sums=N
 def axpy(ctx, alpha, x, y):
     ctx.check(ctx.L.iedg_axpy(ctx.h, x.numel(), float(alpha), _p(x), _p(y), _stream()))
     return y
+
+
+class MinResGuess:
+    """Minimal-residual Newton initial guess (iedg_mr_*, section 2.2.1,
+    eq. MinRes2) for one mesh and element size, workspace for up to s_max
+    previous solutions allocated once."""
+
+    def __init__(self, ctx, mesh, n_local, s_max):
+        self.ctx, self.mesh, self.n, self.s_max = ctx, mesh, int(n_local), int(s_max)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.L.iedg_mr_create(ctx.h, mesh.h, self.n, self.s_max, ctypes.byref(h)))
+        self.h = h
+
+    def residual(self, blocks, G, eps, Z, U, beta, R=None, sums=None):
+        """R(point_k) for the points beta [m][s] (host array): returns R [m][E n + N_t], sums [m]."""
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        m, s = beta.shape
+        A, B, C, D, F = (blocks[k] for k in "ABCDF")
+        _check_dev(A, B, C, D, F, G, Z, U)
+        L = Z.shape[1] * Z.shape[2] + U.shape[1]
+        R = torch.empty((m, L), dtype=torch.float64, device=A.device) if R is None else R
+        sums = torch.empty(m, dtype=torch.float64, device=A.device) if sums is None else sums
+        self.ctx.check(self.ctx.L.iedg_mr_residual(
+            self.ctx.h, self.h, _p(A), _p(B), _p(C), _p(D), _p(F), _p(G), float(eps), s, _p(Z), _p(U), m,
+            beta.ctypes.data_as(ctypes.c_void_p), _p(R), _p(sums), _stream()))
+        return R, sums
+
+    def guess(self, blocks, G, eps, Z, U, max_iters=20, lambda0=1e-3, fd_step=1e-7, tol=1e-10, z0=None, u0=None):
+        """alpha (numpy [s]), z0 [E][n], u0 [N_t] and info dict."""
+        A, B, C, D, F = (blocks[k] for k in "ABCDF")
+        _check_dev(A, B, C, D, F, G, Z, U)
+        s = Z.shape[0]
+        z0 = torch.empty(Z.shape[1:], dtype=torch.float64, device=A.device) if z0 is None else z0
+        u0 = torch.empty(U.shape[1:], dtype=torch.float64, device=A.device) if u0 is None else u0
+        alpha = np.zeros(s)
+        opts = _lib.MrOpts(int(max_iters), float(lambda0), float(fd_step), float(tol))
+        info = _lib.MrInfo()
+        self.ctx.check(self.ctx.L.iedg_mr_guess(
+            self.ctx.h, self.h, _p(A), _p(B), _p(C), _p(D), _p(F), _p(G), float(eps), s, _p(Z), _p(U),
+            ctypes.byref(opts), alpha.ctypes.data_as(ctypes.c_void_p), _p(z0), _p(u0), ctypes.byref(info),
+            _stream()))
+        return alpha, z0, u0, {"iters": info.iters, "passes": info.passes, "obj0": info.obj0, "obj": info.obj}
+
+    def close(self):
+        if self.h:
+            self.ctx.L.iedg_mr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

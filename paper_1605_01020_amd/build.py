@@ -17,7 +17,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wno-unused-result"]
 
 IEDG_SOURCES = ["context.hip", "condense.hip", "condense_f64.hip", "condense_f32.hip", "condense_bf16.hip",
-                "sparse.hip", "mdf.hip", "ras.hip", "krylov.hip", "local.hip"]
+                "sparse.hip", "mdf.hip", "ras.hip", "krylov.hip", "local.hip", "mr.hip"]
 
 
 def _run(cmd):

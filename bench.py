@@ -307,6 +307,45 @@ def extra_rhs_solves(ctx, mesh, n, mats, Fs, Gs, restart):
     return out
 
 
+def extra_mr_guess(ctx, mesh, n, mats, F, G, restart, svals=(3, 6), eps=0.05):
+    """Minimal-residual Newton initial guess (eq. MinRes2) over s previous
+    solutions x_j = (1 + 0.1 (j + 1)) x + 0.01 N(0, 1) around the FP64
+    Newton-step solution x, on the cubic residual with eps: time, passes
+    over the element blocks and the objective reduction."""
+    import numpy as np
+    import torch
+    from paper_1605_01020_amd import api
+    from paper_1605_01020_amd.solver import NewtonStepSolver
+    A, B, C, D = mats
+    solver = NewtonStepSolver(ctx, mesh, n, restart=restart)
+    z, u, _ = solver.solve_fp64(A, B, C, D, F, G, rtol=1e-10)
+    del solver
+    blocks = {"A": A, "B": B, "C": C, "D": D, "F": F}
+    block_bytes = 8 * (A.numel() + B.numel() + C.numel() + D.numel())
+    out = {}
+    for s in svals:
+        g = torch.Generator(device="cuda").manual_seed(s)
+        Z = torch.stack([(1.0 + 0.1 * (j + 1)) * z + 0.01 * torch.randn(z.shape, generator=g, device="cuda",
+                                                                        dtype=torch.float64) for j in range(s)])
+        U = torch.stack([(1.0 + 0.1 * (j + 1)) * u + 0.01 * torch.randn(u.shape, generator=g, device="cuda",
+                                                                        dtype=torch.float64) for j in range(s)])
+        mr = api.MinResGuess(ctx, mesh, n, s)
+        mr.guess(blocks, G, eps, Z, U)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alpha, z0, u0, info = mr.guess(blocks, G, eps, Z, U)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        pass_ms = _ms(lambda: mr.residual(blocks, G, eps, Z, U, np.tile(alpha, (s + 1, 1))), 3)
+        out[f"s{s}"] = {"ms": ms, "passes": info["passes"], "lm_steps": info["iters"],
+                        "pass_ms": pass_ms, "pass_block_TBps": block_bytes / (pass_ms * 1e-3) / 1e12,
+                        "obj_ratio": info["obj"] / info["obj0"], "alpha": [float(a) for a in alpha], "eps": eps}
+        mr.close()
+        del Z, U
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_orderings(ctx, hmesh, spec, mats, F, G, restart, rtol=1e-10):
     """BILU(0) under the natural, colour and minimum discarded fill orders
     (FP64): levels, factorisation and application time, GMRES iterations."""
@@ -508,6 +547,8 @@ def main():
         extras["fp64_rtol_1e-10"] = extra_fp64_tight(ctx, mesh, n, mats, Fs, Gs, wl.restart)
         _log("extra: rhs-only solves with retained factors")
         extras["rhs_solves"] = extra_rhs_solves(ctx, mesh, n, mats, Fs, Gs, wl.restart)
+        _log("extra: minimal-residual Newton initial guess")
+        extras["mr_guess"] = extra_mr_guess(ctx, mesh, n, mats, Fs[0], Gs[0], wl.restart)
         _log("extra: orderings (natural, colour, mdf)")
         extras["orderings_fp64_rtol_1e-10"] = extra_orderings(ctx, hmesh, spec, mats, Fs[0], Gs[0], wl.restart)
         _log("extra: restricted additive Schwarz")

@@ -396,18 +396,20 @@ iedg_status iedg_axpy(iedg_context ctx, int64_t n, double alpha, const double* x
  * iedg_mr_guess: alpha [s] (host), z0 [E][n] and u0 [N_t] (device) = the
  * combination; synchronises `stream` after each pass and each Gram matrix
  * (the s x s damped normal equations are solved on the host).  Algorithm
- * (opts may be NULL: max_iters 20, lambda0 1e-3, fd_step 1e-7, tol 1e-10):
+ * (opts may be NULL: max_iters 20, lambda0 1e-3, fd_step 1e-7, tol 1e-10,
+ * ftol 1e-10):
  * start at alpha = e_1 and lambda0; Jacobian columns by forward differences
  * with steps fd_step max(1, |alpha_i|); step (J^T J + lambda diag(J^T J)) d
  * = -J^T r; accept if the objective decreases (lambda /= 10, floor 1e-12),
  * else lambda *= 10 (at most 10 tries per step); stop after max_iters
  * accepted steps, when no try is accepted, when max|d| <= tol (1 +
- * max|alpha|), or at a zero objective.  info: accepted steps, passes, the
+ * max|alpha|), when an accepted step lowers the objective by no more than
+ * ftol of its value, or at a zero objective.  info: accepted steps, passes, the
  * objective at e_1 and at alpha. */
 typedef struct iedg_mr_s* iedg_mr;
 typedef struct {
   int32_t max_iters;
-  double lambda0, fd_step, tol;
+  double lambda0, fd_step, tol, ftol;
 } iedg_mr_opts;
 typedef struct {
   int32_t iters, passes;

@@ -30,7 +30,8 @@ readings too):
 * accept when the objective decreases (lambda /= 10, floor 1e-12), else
   lambda *= 10 and retry with the same J (at most 10 tries);
 * stop after max_iters accepted steps, when no try is accepted, when
-  max|d| <= tol (1 + max|beta|), or when the objective is zero.
+  max|d| <= tol (1 + max|beta|), when an accepted step lowers the
+  objective by no more than ftol of its value, or when it is zero.
 """
 import numpy as np
 
@@ -74,7 +75,7 @@ def fd_jacobian(res, beta, r0, fd):
     return J
 
 
-def mr_guess(tmesh, blocks, G, eps, Zs, Us, max_iters=20, lambda0=1e-3, fd=1e-7, tol=1e-10):
+def mr_guess(tmesh, blocks, G, eps, Zs, Us, max_iters=20, lambda0=1e-3, fd=1e-7, tol=1e-10, ftol=1e-10):
     """Levenberg-Marquardt for eq. MinRes2.  Returns (alpha, info) with info
     keys obj0 (objective at e_1), obj, iters (accepted steps), evals
     (residual evaluations) and history (objective after each accepted step)."""
@@ -104,6 +105,7 @@ def mr_guess(tmesh, blocks, G, eps, Zs, Us, max_iters=20, lambda0=1e-3, fd=1e-7,
             rt = res(bt)
             ot = float(rt @ rt)
             if ot < obj:
+                decrease = obj - ot
                 beta, r, obj = bt, rt, ot
                 lam = max(lam / 10.0, 1e-12)
                 accepted = True
@@ -113,6 +115,6 @@ def mr_guess(tmesh, blocks, G, eps, Zs, Us, max_iters=20, lambda0=1e-3, fd=1e-7,
             break
         iters += 1
         history.append(obj)
-        if np.max(np.abs(d)) <= tol * (1.0 + np.max(np.abs(beta))):
+        if np.max(np.abs(d)) <= tol * (1.0 + np.max(np.abs(beta))) or decrease <= ftol * (obj + decrease):
             break
     return beta, {"obj0": obj0, "obj": obj, "iters": iters, "evals": evals[0], "history": history}

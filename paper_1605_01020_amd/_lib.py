@@ -36,7 +36,7 @@ class RasInfo(ctypes.Structure):
 
 class MrOpts(ctypes.Structure):
     _fields_ = [("max_iters", c_int32), ("lambda0", ctypes.c_double), ("fd_step", ctypes.c_double),
-                ("tol", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("ftol", ctypes.c_double)]
 
 
 class MrInfo(ctypes.Structure):

@@ -416,7 +416,8 @@ class MinResGuess:
             beta.ctypes.data_as(ctypes.c_void_p), _p(R), _p(sums), _stream()))
         return R, sums
 
-    def guess(self, blocks, G, eps, Z, U, max_iters=20, lambda0=1e-3, fd_step=1e-7, tol=1e-10, z0=None, u0=None):
+    def guess(self, blocks, G, eps, Z, U, max_iters=20, lambda0=1e-3, fd_step=1e-7, tol=1e-10, ftol=1e-10, z0=None,
+              u0=None):
         """alpha (numpy [s]), z0 [E][n], u0 [N_t] and info dict."""
         A, B, C, D, F = (blocks[k] for k in "ABCDF")
         _check_dev(A, B, C, D, F, G, Z, U)
@@ -424,7 +425,7 @@ class MinResGuess:
         z0 = torch.empty(Z.shape[1:], dtype=torch.float64, device=A.device) if z0 is None else z0
         u0 = torch.empty(U.shape[1:], dtype=torch.float64, device=A.device) if u0 is None else u0
         alpha = np.zeros(s)
-        opts = _lib.MrOpts(int(max_iters), float(lambda0), float(fd_step), float(tol))
+        opts = _lib.MrOpts(int(max_iters), float(lambda0), float(fd_step), float(tol), float(ftol))
         info = _lib.MrInfo()
         self.ctx.check(self.ctx.L.iedg_mr_guess(
             self.ctx.h, self.h, _p(A), _p(B), _p(C), _p(D), _p(F), _p(G), float(eps), s, _p(Z), _p(U),

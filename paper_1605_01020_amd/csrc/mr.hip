@@ -434,7 +434,8 @@ extern "C" iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr st, const double*
   if (s < 1 || s > st->s_max) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mr_guess: s=%d (s_max %d)", s, st->s_max);
   const int max_iters = opts ? opts->max_iters : 20;
   const double lambda0 = opts ? opts->lambda0 : 1e-3, fd = opts ? opts->fd_step : 1e-7, tol = opts ? opts->tol : 1e-10;
-  if (max_iters < 0 || !(lambda0 > 0.0) || !(fd > 0.0) || !(tol >= 0.0))
+  const double ftol = opts ? opts->ftol : 1e-10;
+  if (max_iters < 0 || !(lambda0 > 0.0) || !(fd > 0.0) || !(tol >= 0.0) || !(ftol >= 0.0))
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "mr_guess: bad options");
   const MrInputs in{A, B, C, D, F, G, Zprev, Uprev, eps, s};
   const int nv = s + 1;
@@ -488,6 +489,7 @@ extern "C" iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr st, const double*
   }
   while (iters < max_iters && obj > 0.0) {
     bool accepted = false;
+    double decrease = 0.0;
     std::vector<double> d;
     for (int tries = 0; tries < 10; ++tries) {
       std::vector<double> Md(Hm), rhs(s);
@@ -504,6 +506,7 @@ extern "C" iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr st, const double*
       if ((e = read(st->sums, 1)) != IEDG_OK) return e;
       const double ot = h[0];
       if (ot < obj) {
+        decrease = obj - ot;
         cur = 1 - cur;
         beta = bt;
         hs = ht;
@@ -521,7 +524,8 @@ extern "C" iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr st, const double*
       dmax = std::max(dmax, std::fabs(d[i]));
       bmax = std::max(bmax, std::fabs(beta[i]));
     }
-    if (dmax <= tol * (1.0 + bmax) || !(obj > 0.0) || iters >= max_iters) break;
+    if (dmax <= tol * (1.0 + bmax) || decrease <= ftol * (obj + decrease) || !(obj > 0.0) || iters >= max_iters)
+      break;
     if ((e = jacobian(cur, hs)) != IEDG_OK) return e;
   }
   MrPoints Pa{};

@@ -6,8 +6,12 @@ block count nnzb = N_f + 30 E of a structured hex mesh.  ``to_dense`` and
 ``matvec`` are pinned with it (the dense comparison goes through
 ``to_dense``; GMRES on ``matvec`` reproduces the dense solve).
 
-K is returned as a dict {(f, g): b x b block}; every element adds its 36
-face-pair blocks of K_e.  R = G + sum_e P_e^T r_e.
+K is returned as a dict {(f, g): b x b block}; every element adds the
+blocks of K_e of each pair of its local slots (36 face pairs in the
+face-private numbering) to the block of the units they map to, in slot
+order.  R = G + sum_e P_e^T r_e, where P_e^T adds every local dof into its
+global dof (several local dofs of one element may share a global dof in the
+IEDG numbering).
 """
 import numpy as np
 
@@ -18,14 +22,14 @@ def assemble(tmesh, Ks, rs, G):
     for e in range(tmesh.n_elem):
         fs = tmesh.elem_faces[e]
         Ke = Ks[e]
-        for a in range(6):
-            for c in range(6):
+        for a in range(tmesh.slots):
+            for c in range(tmesh.slots):
                 blk = Ke[a * b:(a + 1) * b, c * b:(c + 1) * b]
                 key = (int(fs[a]), int(fs[c]))
                 K[key] = K[key] + blk if key in K else blk.copy()
     R = np.array(G, dtype=np.float64, copy=True)
     for e in range(tmesh.n_elem):
-        R[tmesh.element_dofs(e)] += rs[e]
+        np.add.at(R, tmesh.element_dofs(e), rs[e])
     return K, R
 
 

@@ -52,7 +52,7 @@ def nonlinear_residual(tmesh, blocks, G, eps, z, uhat):
         dofs = tmesh.element_dofs(e)
         ue = uhat[dofs]
         rF[e] = blk["F"] - blk["A"] @ z[e] - blk["B"] @ ue - eps * z[e] ** 3
-        rG[dofs] -= blk["C"] @ z[e] + blk["D"] @ ue
+        np.subtract.at(rG, dofs, blk["C"] @ z[e] + blk["D"] @ ue)
     return rF, rG
 
 

@@ -20,6 +20,6 @@ def full_residual(tmesh, blocks, G, z, uhat):
         rF = blk["F"] - blk["A"] @ z[e] - blk["B"] @ ue
         num += float(rF @ rF)
         den += float(blk["F"] @ blk["F"])
-        rG[dofs] -= blk["C"] @ z[e] + blk["D"] @ ue
+        np.subtract.at(rG, dofs, blk["C"] @ z[e] + blk["D"] @ ue)
     num += float(rG @ rG)
     return np.sqrt(num / den), rG

@@ -78,5 +78,55 @@ class StructuredHexMesh:
                     part[f] = slab_of_elem[e]
         return part
 
+    def iedg_trace_nodes(self, p, m=5):
+        """Trace numbering of the IEDG method (section 2.1: the trace space is
+        continuous on interior faces and discontinuous on boundary faces),
+        with m components per node.  Returns (elem_nodes int32 [E][6 (p+1)^2],
+        n_nodes): the global node of every local trace slot; local trace dof
+        slot * m + c holds component c of that node, so an element's t =
+        6 (p+1)^2 m trace dofs keep the face-private layout (face a, then node
+        q = u (p+1) + v of its (p+1) x (p+1) grid, u and v along the face's
+        two tangential axes in increasing order of x, y, z).
+        A node of an interior face is a point of the (p nx + 1) x (p ny + 1) x
+        (p nz + 1) lattice and is shared by every interior face through it
+        (so also by the faces of one element that meet at an edge); a
+        boundary face has (p+1)^2 nodes of its own.  Nodes are numbered in
+        order of first appearance over faces in id order."""
+        p1 = p + 1
+        d, idx = self.face_geometry()
+        ef = self.elem_faces()
+        # face -> lower corner (element coordinates) and tangential axes
+        corner = np.zeros((self.n_face, 3), dtype=np.int64)
+        for e in range(self.n_elem):
+            ei, ej, ek = e // (self.ny * self.nz), (e // self.nz) % self.ny, e % self.nz
+            for a in range(6):
+                f = ef[e, a]
+                c = [ei, ej, ek]
+                c[d[f]] = idx[f]
+                corner[f] = c
+        nmax = (self.nx, self.ny, self.nz)
+        boundary = np.array([idx[f] == 0 or idx[f] == nmax[d[f]] for f in range(self.n_face)])
+        face_nodes = np.empty((self.n_face, p1 * p1), dtype=np.int64)
+        lattice = {}
+        count = 0
+        for f in range(self.n_face):
+            tang = [x for x in range(3) if x != d[f]]
+            for u in range(p1):
+                for v in range(p1):
+                    if boundary[f]:
+                        face_nodes[f, u * p1 + v] = count
+                        count += 1
+                        continue
+                    P = [p * corner[f, x] for x in range(3)]
+                    P[tang[0]] += u
+                    P[tang[1]] += v
+                    key = tuple(P)
+                    if key not in lattice:
+                        lattice[key] = count
+                        count += 1
+                    face_nodes[f, u * p1 + v] = lattice[key]
+        elem_nodes = face_nodes[ef].reshape(self.n_elem, 6 * p1 * p1)
+        return np.ascontiguousarray(elem_nodes.astype(np.int32)), count
+
     def __repr__(self):
         return f"StructuredHexMesh({self.nx}x{self.ny}x{self.nz})"

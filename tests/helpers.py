@@ -22,9 +22,11 @@ def dense_uncondensed(tmesh, blocks, G):
         d = tmesh.element_dofs(e) + E * n
         loc = np.arange(e * n, (e + 1) * n)
         M[np.ix_(loc, loc)] = blk["A"]
-        M[np.ix_(loc, d)] = blk["B"]
-        M[np.ix_(d, loc)] += blk["C"]
-        M[np.ix_(d, d)] += blk["D"]
+        # add.at: in the IEDG numbering one element may map several local
+        # trace dofs to the same global dof
+        np.add.at(M, (loc[:, None], d[None, :]), blk["B"])
+        np.add.at(M, (d[:, None], loc[None, :]), blk["C"])
+        np.add.at(M, (d[:, None], d[None, :]), blk["D"])
         rhs[loc] = blk["F"]
     rhs[E * n:] = G
     return M, rhs

@@ -95,6 +95,24 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face,
                              int32_t face_dofs, const int32_t* elem_faces,
                              int32_t ordering, const int32_t* order,
                              iedg_mesh* out);
+/* The same for any trace numbering (section 2.1): element e lists `slots`
+ * trace units (elem_units host [n_elem][slots]) of unit_dofs dofs each (unit
+ * u holds dofs u * unit_dofs .. + unit_dofs - 1; the element's t = slots *
+ * unit_dofs local trace dofs are its slots' dofs in slot order).  An element
+ * may list a unit in several slots: the IEDG numbering, whose units are
+ * trace nodes of m components shared along interior faces, does where an
+ * element's own faces meet.  K has a block (u, w) iff u and w appear in a
+ * common element; the block receives Ke_e[a][c] for every element e and
+ * slots a, c mapping to u, w (ascending e, a, c), and P_e^T adds every local
+ * dof into its unit's dof (ascending e, a).  unit_dofs <= 128; every unit
+ * must appear in an element (IEDG_ERR_INVALID_ARG otherwise).  ordering and
+ * layout as for iedg_mesh_create, with units in place of faces;
+ * iedg_mesh_create is this call with slots = 6 and face checks (a face is
+ * listed once by an element and by at most two elements). */
+iedg_status iedg_mesh_create_slots(iedg_context ctx, int32_t n_elem, int32_t slots,
+                                   int32_t n_units, int32_t unit_dofs,
+                                   const int32_t* elem_units, int32_t ordering,
+                                   const int32_t* order, iedg_mesh* out);
 void iedg_mesh_destroy(iedg_mesh mesh);
 
 typedef struct {

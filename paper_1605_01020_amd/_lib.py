@@ -56,6 +56,8 @@ SIGNATURES = {
     "iedg_status_string": (ctypes.c_char_p, [c_int32]),
     "iedg_sync_status": (c_int32, [P, P, ctypes.POINTER(c_int64)]),
     "iedg_mesh_create": (c_int32, [P, c_int32, c_int32, c_int32, P, c_int32, P, ctypes.POINTER(c_void_p)]),
+    "iedg_mesh_create_slots": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, c_int32, P,
+                                         ctypes.POINTER(c_void_p)]),
     "iedg_mesh_destroy": (None, [P]),
     "iedg_mesh_query": (c_int32, [P, ctypes.POINTER(MeshInfo), P, P, P, P]),
     "iedg_condense": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P,

@@ -79,9 +79,12 @@ class Context:
 
 
 class Mesh:
-    """Trace topology + BSR pattern + BILU(0) schedule (iedg_mesh)."""
+    """Trace topology + BSR pattern + BILU(0) schedule (iedg_mesh).
+    elem_faces [E][6]: face-private trace units (iedg_mesh_create); any other
+    width S: element slots of unit_dofs each, e.g. the nodes of the IEDG
+    numbering (iedg_mesh_create_slots; n_face counts the units)."""
 
-    def __init__(self, ctx, elem_faces, n_face, face_dofs, ordering="colour", order=None):
+    def __init__(self, ctx, elem_faces, n_face, face_dofs, ordering="colour", order=None, slots=False):
         self.ctx = ctx
         ef = np.ascontiguousarray(elem_faces, dtype=np.int32)
         code = {"colour": 0, "natural": 1, "given": 2}[ordering]
@@ -90,15 +93,21 @@ class Mesh:
             order = np.ascontiguousarray(order, dtype=np.int32)
             ordp = order.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p()
-        ctx.check(ctx.L.iedg_mesh_create(ctx.h, ef.shape[0], int(n_face), int(face_dofs),
-                                         ef.ctypes.data_as(ctypes.c_void_p), code, ordp,
-                                         ctypes.byref(h)))
+        if ef.shape[1] == 6 and not slots:
+            ctx.check(ctx.L.iedg_mesh_create(ctx.h, ef.shape[0], int(n_face), int(face_dofs),
+                                             ef.ctypes.data_as(ctypes.c_void_p), code, ordp,
+                                             ctypes.byref(h)))
+        else:
+            ctx.check(ctx.L.iedg_mesh_create_slots(ctx.h, ef.shape[0], ef.shape[1], int(n_face), int(face_dofs),
+                                                   ef.ctypes.data_as(ctypes.c_void_p), code, ordp,
+                                                   ctypes.byref(h)))
         self.h = h
         info = MeshInfo()
         ctx.check(ctx.L.iedg_mesh_query(h, ctypes.byref(info), None, None, None, None))
         self.info = info
         self.n_elem, self.n_face, self.b = info.n_elem, info.n_face, info.face_dofs
-        self.t = 6 * self.b
+        self.slots = ef.shape[1]
+        self.t = self.slots * self.b
         self.n_trace, self.nnzb, self.n_levels = info.n_trace, info.nnzb, info.n_levels
 
     def query(self):

@@ -185,46 +185,55 @@ iedg_status iedg_sync_status(iedg_context ctx, hipStream_t stream, int64_t* bad_
   return IEDG_OK;
 }
 
-iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, int32_t face_dofs,
-                             const int32_t* elem_faces, int32_t ordering, const int32_t* order_in,
-                             iedg_mesh* out) {
-  if (!ctx || !out || !elem_faces || n_elem <= 0 || n_face <= 0 || face_dofs <= 0)
-    return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: bad arguments");
-  if (face_dofs > 128)
-    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "mesh_create: face_dofs %d > 128", face_dofs);
-  *out = nullptr;
-  const int E = n_elem, NF = n_face;
-  // element incidence and validity
-  std::vector<std::vector<std::pair<int, int>>> face_elems(NF);
+}  // extern "C"
+
+namespace iedg {
+
+// Mesh of E elements that each list S trace units of b dofs (t = S b).
+static iedg_status mesh_create_general(iedg_context ctx, int E, int S, int NF, int b, const int32_t* eu,
+                                       int ordering, const int32_t* order_in, iedg_mesh* out) {
+  if ((int64_t)E * S * S > INT32_MAX)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "mesh_create: E S^2 = %lld exceeds int32", (long long)E * S * S);
+  // P_e^T sources of every unit, ascending (e, a)
+  std::vector<int32_t> src_ptr(NF + 1, 0), src_list((size_t)E * S);
   for (int e = 0; e < E; ++e)
-    for (int a = 0; a < 6; ++a) {
-      int f = elem_faces[6 * e + a];
-      if (f < 0 || f >= NF) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face id %d out of range", f);
-      for (int a2 = 0; a2 < a; ++a2)
-        if (elem_faces[6 * e + a2] == f)
-          return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: element %d lists face %d twice", e, f);
-      face_elems[f].push_back({e, a});
+    for (int a = 0; a < S; ++a) {
+      const int u = eu[(size_t)S * e + a];
+      if (u < 0 || u >= NF) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: unit id %d out of range", u);
+      src_ptr[u + 1]++;
     }
-  for (int f = 0; f < NF; ++f) {
-    if (face_elems[f].empty()) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face %d has no element", f);
-    if (face_elems[f].size() > 2)
-      return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face %d shared by %zu elements", f, face_elems[f].size());
+  for (int u = 0; u < NF; ++u) {
+    if (src_ptr[u + 1] == 0) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: unit %d has no element", u);
+    src_ptr[u + 1] += src_ptr[u];
   }
-  // coupled faces (pattern), sorted by face id
+  {
+    std::vector<int32_t> fill(src_ptr.begin(), src_ptr.end() - 1);
+    for (int e = 0; e < E; ++e)
+      for (int a = 0; a < S; ++a) src_list[fill[eu[(size_t)S * e + a]]++] = e * S + a;
+  }
+  // coupled units (pattern): units of a common element, sorted by id
   std::vector<std::vector<int>> adj(NF);
-  for (int f = 0; f < NF; ++f) {
-    std::set<int> s;
-    for (auto& ea : face_elems[f])
-      for (int a = 0; a < 6; ++a) s.insert(elem_faces[6 * ea.first + a]);
-    adj[f].assign(s.begin(), s.end());
+  {
+    std::vector<int> us;
+    for (int e = 0; e < E; ++e) {
+      us.assign(eu + (size_t)S * e, eu + (size_t)S * (e + 1));
+      std::sort(us.begin(), us.end());
+      us.erase(std::unique(us.begin(), us.end()), us.end());
+      for (int u : us) adj[u].insert(adj[u].end(), us.begin(), us.end());
+    }
+    for (auto& v : adj) {
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
   }
   auto* m = new iedg_mesh_s();
   m->ctx = ctx;
   m->n_elem = E;
   m->n_face = NF;
-  m->b = face_dofs;
-  m->t = 6 * face_dofs;
-  m->n_trace = int64_t(NF) * face_dofs;
+  m->b = b;
+  m->slots = S;
+  m->t = S * b;
+  m->n_trace = int64_t(NF) * b;
   // ordering
   m->order.resize(NF);
   if (ordering == 1) {
@@ -239,8 +248,8 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
       m->order[i] = f;
     }
   } else if (ordering == 0) {
-    // greedy colouring: ascending face id, smallest colour not used by an
-    // already coloured coupled face; rows listed by (colour, face id)
+    // greedy colouring: ascending unit id, smallest colour not used by an
+    // already coloured coupled unit; rows listed by (colour, unit id)
     std::vector<int> colour(NF, -1);
     int ncol = 0;
     for (int f = 0; f < NF; ++f) {
@@ -265,28 +274,37 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
     iedg_mesh_destroy(m);
     return st;
   }
-  // assembly gather map: block (f, g) receives Ke_e[a][c] for every element e
-  // holding f at local face a and g at local face c (ascending e)
-  std::vector<int32_t> asm_src(2 * m->nnzb, -1);
-  for (int i = 0; i < NF; ++i) {
-    int f = m->order[i];
-    for (int s = m->row_ptr[i]; s < m->row_ptr[i + 1]; ++s) {
-      int g = m->col_face[s], k = 0;
-      for (auto& ea : face_elems[f]) {
-        int e = ea.first;
-        for (int c = 0; c < 6; ++c)
-          if (elem_faces[6 * e + c] == g) asm_src[2 * s + (k++)] = e * 36 + ea.second * 6 + c;
+  // assembly lists: block (u_a, u_c) receives Ke_e[a][c]; the block of a
+  // pair is found by bisection over its row's columns (sorted by position)
+  std::vector<int32_t> slot_of((size_t)E * S * S);
+  for (int e = 0; e < E; ++e)
+    for (int a = 0; a < S; ++a) {
+      const int i = m->pos[eu[(size_t)S * e + a]];
+      const int r0 = m->row_ptr[i], r1 = m->row_ptr[i + 1];
+      for (int c = 0; c < S; ++c) {
+        const int pc = m->pos[eu[(size_t)S * e + c]];
+        int lo = r0, hi = r1;
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if (m->pos[m->col_face[mid]] < pc) lo = mid + 1;
+          else hi = mid;
+        }
+        slot_of[((size_t)e * S + a) * S + c] = lo;
       }
     }
+  std::vector<int32_t> asm_ptr(m->nnzb + 1, 0), asm_list((size_t)E * S * S);
+  for (int32_t sl : slot_of) asm_ptr[sl + 1]++;
+  for (int64_t s = 0; s < m->nnzb; ++s) asm_ptr[s + 1] += asm_ptr[s];
+  {
+    std::vector<int32_t> fill(asm_ptr.begin(), asm_ptr.end() - 1);
+    for (size_t code = 0; code < slot_of.size(); ++code) asm_list[fill[slot_of[code]]++] = (int32_t)code;
   }
-  std::vector<int32_t> face_src(2 * NF, -1);
-  for (int f = 0; f < NF; ++f)
-    for (size_t k = 0; k < face_elems[f].size(); ++k)
-      face_src[2 * f + k] = face_elems[f][k].first * 6 + face_elems[f][k].second;
-  std::vector<int32_t> ef(elem_faces, elem_faces + 6 * (size_t)E);
+  std::vector<int32_t> ef(eu, eu + (size_t)S * E);
   if (st == IEDG_OK) st = upload(ctx, &m->d_elem_faces, ef);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_asm_src, asm_src);
-  if (st == IEDG_OK) st = upload(ctx, &m->d_face_src, face_src);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_asm_ptr, asm_ptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_asm_list, asm_list);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_src_ptr, src_ptr);
+  if (st == IEDG_OK) st = upload(ctx, &m->d_src_list, src_list);
   if (st == IEDG_OK) {
     const size_t rw = (size_t)E * m->t + 2 * (size_t)E + 2 * (size_t)NF;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&m->d_rwork), rw * sizeof(double));
@@ -300,10 +318,48 @@ iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, i
   return IEDG_OK;
 }
 
+}  // namespace iedg
+
+extern "C" {
+
+iedg_status iedg_mesh_create(iedg_context ctx, int32_t n_elem, int32_t n_face, int32_t face_dofs,
+                             const int32_t* elem_faces, int32_t ordering, const int32_t* order_in,
+                             iedg_mesh* out) {
+  if (!ctx || !out || !elem_faces || n_elem <= 0 || n_face <= 0 || face_dofs <= 0)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: bad arguments");
+  if (face_dofs > 128)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "mesh_create: face_dofs %d > 128", face_dofs);
+  *out = nullptr;
+  // faces: listed at most once by an element, by at most two elements
+  std::vector<int> count(n_face, 0);
+  for (int e = 0; e < n_elem; ++e)
+    for (int a = 0; a < 6; ++a) {
+      const int f = elem_faces[6 * e + a];
+      if (f < 0 || f >= n_face) return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face id %d out of range", f);
+      for (int a2 = 0; a2 < a; ++a2)
+        if (elem_faces[6 * e + a2] == f)
+          return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: element %d lists face %d twice", e, f);
+      if (++count[f] > 2)
+        return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create: face %d shared by more than two elements", f);
+    }
+  return mesh_create_general(ctx, n_elem, 6, n_face, face_dofs, elem_faces, ordering, order_in, out);
+}
+
+iedg_status iedg_mesh_create_slots(iedg_context ctx, int32_t n_elem, int32_t slots, int32_t n_units,
+                                   int32_t unit_dofs, const int32_t* elem_units, int32_t ordering,
+                                   const int32_t* order_in, iedg_mesh* out) {
+  if (!ctx || !out || !elem_units || n_elem <= 0 || slots <= 0 || n_units <= 0 || unit_dofs <= 0)
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "mesh_create_slots: bad arguments");
+  if (unit_dofs > 128)
+    return set_error(ctx, IEDG_ERR_UNSUPPORTED, "mesh_create_slots: unit_dofs %d > 128", unit_dofs);
+  *out = nullptr;
+  return mesh_create_general(ctx, n_elem, slots, n_units, unit_dofs, elem_units, ordering, order_in, out);
+}
+
 void iedg_mesh_destroy(iedg_mesh m) {
   if (!m) return;
   int32_t* ptrs[] = {m->d_elem_faces, m->d_row_face, m->d_pos, m->d_row_ptr, m->d_col_face,
-                     m->d_diag_slot, m->d_level_rows, m->d_asm_src, m->d_face_src,
+                     m->d_diag_slot, m->d_level_rows, m->d_asm_ptr, m->d_asm_list, m->d_src_ptr, m->d_src_list,
                      m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd};
   for (int32_t* p : ptrs)
     if (p) hipFree(p);

@@ -17,7 +17,7 @@ constexpr int LWAVES = LTHR / 64;
 // the storage precision and solved by one wave.  LDS stays small so that
 // several elements share a CU.
 template <typename T>
-__global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, const int32_t* elem_faces, const T* LU,
+__global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, int S, const int32_t* elem_faces, const T* LU,
                                                          const int32_t* perm, const T* U12, const double* w,
                                                          const double* uhat, double* z) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < t; i += LTHR) {
     const int a = i / b, l = i % b;
-    ue[i] = uhat[(size_t)elem_faces[6 * e + a] * b + l];
+    ue[i] = uhat[(size_t)elem_faces[S * e + a] * b + l];
   }
   for (int i = tid; i < n; i += LTHR) sp[i] = perm[(size_t)e * n + i];
   __syncthreads();
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(LTHR) void backsolve_kernel(int n, int t, int b, co
 
 // Per element: rF_e = F_e - A_e z_e - B_e u_e; q_e = C_e z_e + D_e u_e; also
 // per-element sums of rF^2 and F^2 (fixed-order block reduction).
-__global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b, const int32_t* elem_faces,
+__global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b, int S, const int32_t* elem_faces,
                                                              const double* A, const double* B, const double* C,
                                                              const double* D, const double* F, const double* z,
                                                              const double* uhat, double* rF, double* q,
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b
   const int e = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < t; i += LTHR) {
     const int a = i / b, l = i % b;
-    ue[i] = uhat[(size_t)elem_faces[6 * e + a] * b + l];
+    ue[i] = uhat[(size_t)elem_faces[S * e + a] * b + l];
   }
   for (int i = tid; i < n; i += LTHR) ze[i] = z[(size_t)e * n + i];
   __syncthreads();
@@ -132,8 +132,10 @@ __global__ __launch_bounds__(LTHR) void residual_elem_kernel(int n, int t, int b
   }
 }
 
-// rG = G - sum_e P_e^T q_e (ascending e) and per-face sums of rG^2, G^2.
-__global__ __launch_bounds__(128) void residual_face_kernel(int b, int t, const int32_t* face_src, const double* q,
+// rG = G - sum_e P_e^T q_e (list order: ascending e, a) and per-unit sums of
+// rG^2, G^2 (b <= 128 dofs a unit, one workgroup of 128 threads a unit).
+__global__ __launch_bounds__(128) void residual_face_kernel(int b, int t, int S, const int32_t* src_ptr,
+                                                            const int32_t* src_list, const double* q,
                                                             const double* G, double* rG, double* part_rg,
                                                             double* part_g) {
   __shared__ double red[2];
@@ -143,9 +145,9 @@ __global__ __launch_bounds__(128) void residual_face_kernel(int b, int t, const 
     const size_t i = (size_t)f * b + l;
     g = G[i];
     v = g;
-    for (int k = 0; k < 2; ++k) {
-      const int src = face_src[2 * f + k];
-      if (src >= 0) v -= q[(size_t)(src / 6) * t + (src % 6) * b + l];
+    for (int k = src_ptr[f]; k < src_ptr[f + 1]; ++k) {
+      const int code = src_list[k], e = code / S, a = code - e * S;
+      v -= q[(size_t)e * t + a * b + l];
     }
     rG[i] = v;
   }
@@ -187,13 +189,13 @@ extern "C" iedg_status iedg_backsolve_local(iedg_context ctx, iedg_mesh mesh, in
     const size_t smem = smem_ints + sizeof(double) * 64 * 65;
     auto k = backsolve_kernel<double>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
+    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->slots, mesh->d_elem_faces,
                        (const double*)LU, perm, (const double*)U12, w, uhat, z);
   } else {
     const size_t smem = smem_ints + sizeof(float) * 64 * 65;
     auto k = backsolve_kernel<float>;
     IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces,
+    hipLaunchKernelGGL(k, dim3(mesh->n_elem), dim3(LTHR), smem, stream, n, t, b, mesh->slots, mesh->d_elem_faces,
                        (const float*)LU, perm, (const float*)U12, w, uhat, z);
   }
   IEDG_LAUNCH_CHECK(ctx, "backsolve launch");
@@ -217,9 +219,10 @@ static iedg_status residual_launch(iedg_context ctx, iedg_mesh mesh, int n, cons
   const size_t smem = sizeof(double) * (t + n + 3 * LWAVES);
   IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(residual_elem_kernel),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  hipLaunchKernelGGL(residual_elem_kernel, dim3(E), dim3(LTHR), smem, stream, n, t, b, mesh->d_elem_faces, A, B, C, D,
+  hipLaunchKernelGGL(residual_elem_kernel, dim3(E), dim3(LTHR), smem, stream, n, t, b, mesh->slots, mesh->d_elem_faces, A, B, C, D,
                      F, z, uhat, rF, q, prf, pf);
-  hipLaunchKernelGGL(residual_face_kernel, dim3(NF), dim3(128), 0, stream, b, t, mesh->d_face_src, q, G, rG, prg, pg);
+  hipLaunchKernelGGL(residual_face_kernel, dim3(NF), dim3(128), 0, stream, b, t, mesh->slots, mesh->d_src_ptr,
+                     mesh->d_src_list, q, G, rG, prg, pg);
   hipLaunchKernelGGL(sum4_kernel, dim3(4), dim3(64), 0, stream, prf, (int64_t)E, prg, (int64_t)NF, pf, (int64_t)E, pg,
                      (int64_t)NF, sums);
   IEDG_LAUNCH_CHECK(ctx, "residual launch");

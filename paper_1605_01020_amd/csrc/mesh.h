@@ -3,9 +3,11 @@
 
 #include "common.h"
 
+// Rows ("faces" below) are the trace units: faces with private dofs, or the
+// nodes of the IEDG numbering; element e lists `slots` units, t = slots b.
 struct iedg_mesh_s {
   iedg_context ctx = nullptr;
-  int32_t n_elem = 0, n_face = 0, b = 0, t = 0;
+  int32_t n_elem = 0, n_face = 0, b = 0, t = 0, slots = 6;
   int64_t n_trace = 0, nnzb = 0;
   int32_t n_levels = 0;
   int64_t n_lslots = 0, n_updates = 0;
@@ -20,15 +22,21 @@ struct iedg_mesh_s {
   std::vector<int32_t> diag_slot;   // [n_face]
 
   // device copies
-  int32_t* d_elem_faces = nullptr;  // [E][6]
+  int32_t* d_elem_faces = nullptr;  // [E][slots]: unit of each local slot
   int32_t* d_row_face = nullptr;    // [n_face]
   int32_t* d_pos = nullptr;         // [n_face]: face -> row
   int32_t* d_row_ptr = nullptr;     // [n_face + 1]
   int32_t* d_col_face = nullptr;    // [nnzb]
   int32_t* d_diag_slot = nullptr;   // [n_face]
   int32_t* d_level_rows = nullptr;  // [n_face]
-  int32_t* d_asm_src = nullptr;     // [nnzb][2]: e*36 + a*6 + c or -1
-  int32_t* d_face_src = nullptr;    // [n_face][2]: e*6 + a or -1
+  // assembly of K: block s receives Ke_e[a][c] for every code e*S*S + a*S + c
+  // in asm_list[asm_ptr[s] .. asm_ptr[s+1]) (ascending: e, then a, then c)
+  int32_t* d_asm_ptr = nullptr;     // [nnzb + 1]
+  int32_t* d_asm_list = nullptr;    // [E * slots^2]
+  // P_e^T: unit u receives slot a of element e for every code e*S + a in
+  // src_list[src_ptr[u] .. src_ptr[u+1]) (ascending)
+  int32_t* d_src_ptr = nullptr;     // [n_face + 1]
+  int32_t* d_src_list = nullptr;    // [E * slots]
   int32_t* d_ilu_lptr = nullptr;    // [n_face + 1] into ilu_l (per row)
   int32_t* d_ilu_l = nullptr;       // [n_lslots][2]: slot (i,k), diag slot of k
   int32_t* d_ilu_uptr = nullptr;    // [n_lslots + 1] into ilu_upd

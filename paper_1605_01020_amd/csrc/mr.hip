@@ -70,7 +70,7 @@ __device__ __forceinline__ void row_dots(const double* __restrict__ row, const d
 // row of [A B] the residual R_NS of every point, per row of [C D] the
 // element's contribution q = C z + D uhat of every point, and per point the
 // element's sum of R_NS^2.
-__global__ __launch_bounds__(MR_THR) void mr_elem_kernel(int n, int t, int b, int E, const int32_t* elem_faces,
+__global__ __launch_bounds__(MR_THR) void mr_elem_kernel(int n, int t, int b, int S, int E, const int32_t* elem_faces,
                                                          const double* __restrict__ A, const double* __restrict__ B,
                                                          const double* __restrict__ C, const double* __restrict__ D,
                                                          const double* __restrict__ F, const double* __restrict__ Z,
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(MR_THR) void mr_elem_kernel(int n, int t, int b, in
   }
   for (int i = tid; i < t; i += MR_THR) {
     const int a = i / b, l = i - a * b;
-    const size_t g = (size_t)elem_faces[6 * e + a] * b + l;
+    const size_t g = (size_t)elem_faces[S * e + a] * b + l;
     double xj[MR_MAXS];
 #pragma unroll
     for (int j = 0; j < MR_MAXS; ++j) xj[j] = j < s ? U[(size_t)j * Nt + g] : 0.0;
@@ -159,10 +159,11 @@ __global__ __launch_bounds__(MR_THR) void mr_elem_kernel(int n, int t, int b, in
   }
 }
 
-// One workgroup (128 threads) per face: R_FL of every point on the face's b
-// dofs (contributions of its one or two elements in ascending element
-// order) and the face's sum of R_FL^2 per point.
-__global__ __launch_bounds__(128) void mr_face_kernel(int b, int t, int E, int NF, const int32_t* face_src,
+// One workgroup (128 threads) per trace unit: R_FL of every point on the
+// unit's b dofs (contributions of its element slots in ascending order) and
+// the unit's sum of R_FL^2 per point.
+__global__ __launch_bounds__(128) void mr_face_kernel(int b, int t, int S, int E, int NF, const int32_t* src_ptr,
+                                                      const int32_t* src_list,
                                                       const double* q, const double* G, const double* U, int64_t Nt,
                                                       double eps, MrPoints P, double* R, int64_t L, int64_t En,
                                                       double* part) {
@@ -177,7 +178,7 @@ __global__ __launch_bounds__(128) void mr_face_kernel(int b, int t, int E, int N
 #pragma unroll
     for (int j = 0; j < MR_MAXS; ++j) xj[j] = j < s ? U[(size_t)j * Nt + i] : 0.0;
     const double g = G[i];
-    const int s0 = face_src[2 * f], s1 = face_src[2 * f + 1];
+    const int k0 = src_ptr[f], k1 = src_ptr[f + 1];
 #pragma unroll
     for (int k = 0; k < MR_MAXM; ++k) {
       if (k < m) {
@@ -186,8 +187,10 @@ __global__ __launch_bounds__(128) void mr_face_kernel(int b, int t, int E, int N
         for (int j = 0; j < MR_MAXS; ++j)
           if (j < s) u += P.beta[k][j] * xj[j];
         double v = g;
-        if (s0 >= 0) v -= q[((size_t)k * E + s0 / 6) * t + (s0 % 6) * b + l];
-        if (s1 >= 0) v -= q[((size_t)k * E + s1 / 6) * t + (s1 % 6) * b + l];
+        for (int c = k0; c < k1; ++c) {
+          const int code = src_list[c], e = code / S, a = code - e * S;
+          v -= q[((size_t)k * E + e) * t + a * b + l];
+        }
         v -= eps * u * u * u;
         R[(size_t)k * L + En + i] = v;
         sq[k] = v * v;
@@ -353,9 +356,10 @@ iedg_status mr_pass(iedg_mr st, const MrInputs& in, const MrPoints& P, double* R
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
   double* pe = st->part;
   double* pf = st->part + (size_t)P.m * E;
-  hipLaunchKernelGGL(mr_elem_kernel, dim3(E), dim3(MR_THR), smem, stream, n, t, b, E, mesh->d_elem_faces, in.A, in.B,
+  hipLaunchKernelGGL(mr_elem_kernel, dim3(E), dim3(MR_THR), smem, stream, n, t, b, mesh->slots, E, mesh->d_elem_faces, in.A, in.B,
                      in.C, in.D, in.F, in.Z, in.U, (int64_t)mesh->n_trace, in.eps, P, R, st->L, st->q, pe);
-  hipLaunchKernelGGL(mr_face_kernel, dim3(NF), dim3(128), 0, stream, b, t, E, NF, mesh->d_face_src, st->q, in.G, in.U,
+  hipLaunchKernelGGL(mr_face_kernel, dim3(NF), dim3(128), 0, stream, b, t, mesh->slots, E, NF, mesh->d_src_ptr,
+                     mesh->d_src_list, st->q, in.G, in.U,
                      (int64_t)mesh->n_trace, in.eps, P, R, st->L, (int64_t)E * n, pf);
   hipLaunchKernelGGL(mr_sum_kernel, dim3(P.m), dim3(64), 0, stream, pe, E, pf, NF, sums);
   IEDG_LAUNCH_CHECK(ctx, "mr pass launch");

@@ -11,34 +11,41 @@
 namespace iedg {
 
 // ---- assembly ----------------------------------------------------------
-// One workgroup per BSR block: gather the (one or two) element sub-blocks
-// Ke_e[a*b:(a+1)*b, c*b:(c+1)*b] (row-major t x t), sum in ascending element
-// order and write the block transposed to column-major through LDS.
+// Block s of K is the sum, in list order (ascending element, then local
+// slots), of the sub-blocks Ke_e[a*b:(a+1)*b, c*b:(c+1)*b] (row-major t x t)
+// coded e*S*S + a*S + c in asm_list[asm_ptr[s] .. asm_ptr[s+1]).
+__device__ __forceinline__ size_t asm_offset(int code, int S, int b, int t) {
+  const int e = code / (S * S), ac = code - e * S * S, a = ac / S, c = ac - a * S;
+  return (size_t)e * t * t + (size_t)a * b * t + (size_t)c * b;
+}
+
+// One workgroup per block (face units): the summed block is transposed to
+// column-major through LDS.
 template <typename T>
-__global__ __launch_bounds__(STHR) void assemble_k_kernel(int b, int t, const int32_t* asm_src, const T* Ke,
-                                                          T* Kbsr) {
+__global__ __launch_bounds__(STHR) void assemble_k_kernel(int b, int t, int S, const int32_t* asm_ptr,
+                                                          const int32_t* asm_list, const T* Ke, T* Kbsr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);  // b x (b+1)
   const int64_t s = blockIdx.x;
-  const int src0 = asm_src[2 * s], src1 = asm_src[2 * s + 1];
+  const int k0 = asm_ptr[s], k1 = asm_ptr[s + 1];
   const int bb = b * b;
-  const size_t tt = (size_t)t * t;
-  const T* p0 = Ke + (size_t)(src0 / 36) * tt + (size_t)((src0 % 36) / 6) * b * t + (size_t)(src0 % 6) * b;
-  const T* p1 = src1 >= 0 ? Ke + (size_t)(src1 / 36) * tt + (size_t)((src1 % 36) / 6) * b * t + (size_t)(src1 % 6) * b
-                          : nullptr;
   for (int i0 = threadIdx.x; i0 < bb; i0 += STHR * 8) {
-    T v0[8], v1[8];
+    T v[8];
+    for (int k = k0; k < k1; ++k) {
+      const T* p = Ke + asm_offset(asm_list[k], S, b, t);
+      T x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = i0 + STHR * j;
-      const int rr = i / b, cc = i % b;
-      v0[j] = i < bb ? p0[(size_t)rr * t + cc] : T(0);
-      v1[j] = (p1 && i < bb) ? p1[(size_t)rr * t + cc] : T(0);
+      for (int j = 0; j < 8; ++j) {
+        const int i = i0 + STHR * j;
+        x[j] = i < bb ? p[(size_t)(i / b) * t + i % b] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = k == k0 ? x[j] : v[j] + x[j];
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = i0 + STHR * j;
-      if (i < bb) tile[(i / b) * (b + 1) + i % b] = p1 ? v0[j] + v1[j] : v0[j];
+      if (i < bb) tile[(i / b) * (b + 1) + i % b] = v[j];
     }
   }
   __syncthreads();
@@ -49,17 +56,36 @@ __global__ __launch_bounds__(STHR) void assemble_k_kernel(int b, int t, const in
   }
 }
 
-// R[f*b + l] = G[f*b + l] + sum over elements e (ascending) of r_e[a*b + l].
-__global__ void assemble_r_kernel(int n_face, int b, int t, const int32_t* face_src, const double* r,
-                                  const double* G, double* R) {
+// Small blocks (node units): one thread per block entry, written directly
+// in column-major order; same summation order.
+template <typename T>
+__global__ void assemble_k_small_kernel(int b, int t, int S, int64_t nnzb, const int32_t* asm_ptr,
+                                        const int32_t* asm_list, const T* Ke, T* Kbsr) {
+  const int bb = b * b;
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nnzb * bb) return;
+  const int64_t s = x / bb;
+  const int i = (int)(x - s * bb), cc = i / b, rr = i - cc * b;
+  T v = T(0);
+  for (int k = asm_ptr[s]; k < asm_ptr[s + 1]; ++k) {
+    const T y = Ke[asm_offset(asm_list[k], S, b, t) + (size_t)rr * t + cc];
+    v = k == asm_ptr[s] ? y : v + y;
+  }
+  Kbsr[x] = v;
+}
+
+// R[u*b + l] = G[u*b + l] + sum, in list order (ascending e, a), of
+// r_e[a*b + l] over the slots coded e*S + a in src_list[src_ptr[u] ..].
+__global__ void assemble_r_kernel(int n_face, int b, int t, int S, const int32_t* src_ptr, const int32_t* src_list,
+                                  const double* r, const double* G, double* R) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)n_face * b) return;
   const int f = (int)(i / b), l = (int)(i % b);
   double v = G ? G[i] : 0.0;
   if (r) {
-    for (int k = 0; k < 2; ++k) {
-      const int src = face_src[2 * f + k];
-      if (src >= 0) v += r[(size_t)(src / 6) * t + (src % 6) * b + l];
+    for (int k = src_ptr[f]; k < src_ptr[f + 1]; ++k) {
+      const int code = src_list[k], e = code / S, a = code - e * S;
+      v += r[(size_t)e * t + a * b + l];
     }
   }
   R[i] = v;
@@ -564,24 +590,35 @@ iedg_status iedg_assemble(iedg_context ctx, iedg_mesh m, iedg_prec prec, const v
   if (prec != IEDG_F64 && prec != IEDG_F32 && prec != IEDG_BF16)
     return set_error(ctx, IEDG_ERR_INVALID_ARG, "assemble: precision");
   if (Ke) {
-    const size_t smem = prec_size(prec) * m->b * (m->b + 1);
-    if (prec == IEDG_F64) {
-      auto k = assemble_k_kernel<double>;
-      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->d_asm_src, (const double*)Ke,
-                         (double*)Kbsr);
+    if (m->b < 16) {
+      const int64_t total = m->nnzb * m->b * m->b;
+      const unsigned grid = (unsigned)((total + 255) / 256);
+      if (prec == IEDG_F64)
+        hipLaunchKernelGGL(assemble_k_small_kernel<double>, dim3(grid), dim3(256), 0, stream, m->b, m->t, m->slots,
+                           m->nnzb, m->d_asm_ptr, m->d_asm_list, (const double*)Ke, (double*)Kbsr);
+      else
+        hipLaunchKernelGGL(assemble_k_small_kernel<float>, dim3(grid), dim3(256), 0, stream, m->b, m->t, m->slots,
+                           m->nnzb, m->d_asm_ptr, m->d_asm_list, (const float*)Ke, (float*)Kbsr);
     } else {
-      auto k = assemble_k_kernel<float>;
-      IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-      hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->d_asm_src, (const float*)Ke,
-                         (float*)Kbsr);
+      const size_t smem = prec_size(prec) * m->b * (m->b + 1);
+      if (prec == IEDG_F64) {
+        auto k = assemble_k_kernel<double>;
+        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->slots, m->d_asm_ptr,
+                           m->d_asm_list, (const double*)Ke, (double*)Kbsr);
+      } else {
+        auto k = assemble_k_kernel<float>;
+        IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        hipLaunchKernelGGL(k, dim3(m->nnzb), dim3(STHR), smem, stream, m->b, m->t, m->slots, m->d_asm_ptr,
+                           m->d_asm_list, (const float*)Ke, (float*)Kbsr);
+      }
     }
     IEDG_LAUNCH_CHECK(ctx, "assemble K launch");
   }
   if (R) {
     const int64_t total = m->n_trace;
     hipLaunchKernelGGL(assemble_r_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, m->n_face,
-                       m->b, m->t, m->d_face_src, r, G, R);
+                       m->b, m->t, m->slots, m->d_src_ptr, m->d_src_list, r, G, R);
     IEDG_LAUNCH_CHECK(ctx, "assemble R launch");
   }
   return IEDG_OK;

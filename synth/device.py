@@ -70,9 +70,11 @@ def gen_blocks(spec, seed, mesh_id, n_elem, which="ABCD", rhs=0, elem0=0, out=No
     return res
 
 
-def gen_trace_rhs(spec, seed, mesh_id, n_face, rhs=0, out=None):
+def gen_trace_rhs(spec, seed, mesh_id, n_face, rhs=0, out=None, count=None):
+    """G on the device: n_face * b values, or the first `count` of the same
+    stream (the trace size of another numbering)."""
     import torch
-    total = n_face * spec.b
+    total = n_face * spec.b if count is None else int(count)
     if out is None:
         out = torch.empty(total, dtype=torch.float64, device="cuda")
     diag, sigma = dist_params(spec, MAT_G)

@@ -549,6 +549,175 @@ iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, co
 
 }  // namespace iedg
 
+// ---- BILU(0) of small blocks (b <= 8: the m x m node blocks of the IEDG
+// numbering) ----------------------------------------------------------------
+// One wave per block row (4 rows a workgroup, no barriers).  For each lower
+// slot (i, k) in elimination order every lane forms L_ik = A_ik U_kk^{-1} in
+// registers (the blocks are broadcast loads); lane 0 stores it, and the
+// updates A_ij -= L_ik U_kj of that slot are dealt to the lanes, one block
+// each.  The updated blocks are made visible to the whole wave (stores
+// complete, vector L1 invalidated) before the next slot reads its A_ik.
+// Lane 0 then inverts the pivot block by Gauss-Jordan with partial pivoting
+// in exchange form (no row moves: the inverse is written through the
+// recorded pivot rows and steps).
+template <typename T, int B>
+__device__ __forceinline__ void small_load(const T* __restrict__ p, T (&x)[B * B]) {
+#pragma unroll
+  for (int q = 0; q < B * B; ++q) x[q] = p[q];
+}
+
+// C = A B (column-major b x b: entry (r, c) at c B + r), or C -= A B.
+template <typename T, int B, bool SUB>
+__device__ __forceinline__ void small_mm(const T (&a)[B * B], const T (&b)[B * B], T (&c)[B * B]) {
+#pragma unroll
+  for (int col = 0; col < B; ++col)
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      T v = T(0);
+#pragma unroll
+      for (int k = 0; k < B; ++k) v += a[k * B + r] * b[col * B + k];
+      c[col * B + r] = SUB ? c[col * B + r] - v : v;
+    }
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(256) void ilu0_small_kernel(int nrows, const int32_t* __restrict__ rows,
+                                                         const int32_t* __restrict__ diag_slot,
+                                                         const int32_t* __restrict__ lptr,
+                                                         const int32_t* __restrict__ lslot,
+                                                         const int32_t* __restrict__ uptr,
+                                                         const int32_t* __restrict__ upd, T* M,
+                                                         DeviceStatus* status) {
+  constexpr int BB = B * B;
+  const int lane = threadIdx.x & 63;
+  const int rr = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (rr >= nrows) return;
+  const int i = rows[rr];
+  const int l0 = lptr[i], l1 = lptr[i + 1];
+  // read-only operands of the next slot (its U_kk^{-1} and this lane's first
+  // U_kj, from rows of earlier levels) are loaded one slot ahead; A_ik and
+  // the lane's first A_ij are loaded together right after the previous
+  // slot's updates are visible
+  T un[BB], ukn[BB];
+  if (l0 < l1) {
+    small_load<T, B>(M + (size_t)lslot[2 * l0 + 1] * BB, un);
+    const int x0 = uptr[l0] + lane;
+    if (x0 < uptr[l0 + 1]) small_load<T, B>(M + (size_t)upd[2 * x0] * BB, ukn);
+  }
+  for (int l = l0; l < l1; ++l) {
+    const int sik = lslot[2 * l];
+    const int xb = uptr[l], xe = uptr[l + 1];
+    T a[BB], u[BB], L[BB], uk0[BB], c0[BB];
+    small_load<T, B>(M + (size_t)sik * BB, a);
+    if (xb + lane < xe) small_load<T, B>(M + (size_t)upd[2 * (xb + lane) + 1] * BB, c0);
+#pragma unroll
+    for (int q = 0; q < BB; ++q) {
+      u[q] = un[q];
+      uk0[q] = ukn[q];
+    }
+    if (l + 1 < l1) {
+      small_load<T, B>(M + (size_t)lslot[2 * (l + 1) + 1] * BB, un);
+      const int x1 = xe + lane;
+      if (x1 < uptr[l + 2]) small_load<T, B>(M + (size_t)upd[2 * x1] * BB, ukn);
+    }
+    small_mm<T, B, false>(a, u, L);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < BB; ++q) M[(size_t)sik * BB + q] = L[q];
+    if (xb + lane < xe) {
+      small_mm<T, B, true>(L, uk0, c0);
+      T* C = M + (size_t)upd[2 * (xb + lane) + 1] * BB;
+#pragma unroll
+      for (int q = 0; q < BB; ++q) C[q] = c0[q];
+    }
+    for (int x = xb + lane + 64; x < xe; x += 64) {
+      T* C = M + (size_t)upd[2 * x + 1] * BB;
+      T ukj[BB], c[BB];
+      small_load<T, B>(M + (size_t)upd[2 * x] * BB, ukj);
+      small_load<T, B>(C, c);
+      small_mm<T, B, true>(L, ukj, c);
+#pragma unroll
+      for (int q = 0; q < BB; ++q) C[q] = c[q];
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    asm volatile("buffer_inv sc0" ::: "memory");
+  }
+  if (lane != 0) return;
+  T* Dg = M + (size_t)diag_slot[i] * BB;
+  T W[B][B];
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c) W[r][c] = Dg[c * B + r];
+  bool piv[B];
+  int step[B], prow[B];
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+    piv[r] = false;
+    step[r] = 0;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    // largest magnitude in column k among unpivoted rows, ties to the smaller
+    // row; NaN is never larger, so the first unpivoted row stands in
+    int p = -1;
+    double best = -1.0;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const double v = fabs((double)W[r][k]);
+      if (!piv[r] && (p < 0 || v > best)) {
+        best = v;
+        p = r;
+      }
+    }
+    if (!(best > 0.0) || !(best <= DBL_MAX)) ok = false;
+    T pr[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      T v = W[0][c];
+#pragma unroll
+      for (int r = 1; r < B; ++r) v = r == p ? W[r][c] : v;
+      pr[c] = v;
+    }
+    const T ip = T(1) / pr[k];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      if (r == p) {
+#pragma unroll
+        for (int c = 0; c < B; ++c) W[r][c] = c == k ? ip : -(pr[c] * ip);
+        piv[r] = true;
+        step[r] = k;
+      } else {
+        const T v = W[r][k];
+#pragma unroll
+        for (int c = 0; c < B; ++c) W[r][c] = c == k ? v * ip : W[r][c] - v * (pr[c] * ip);
+      }
+    }
+    prow[k] = p;
+  }
+  // inverse(step(r), prow(c)) = W(r, c)
+#pragma unroll
+  for (int r = 0; r < B; ++r)
+#pragma unroll
+    for (int c = 0; c < B; ++c) Dg[prow[c] * B + step[r]] = W[r][c];
+  if (!ok) latch_status(status, IEDG_ERR_SINGULAR, i);
+}
+
+template <typename T, int B>
+static iedg_status factor_levels_small(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
+  auto kern = ilu0_small_kernel<T, B>;
+  for (int l = 0; l < m->n_levels; ++l) {
+    const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(kern, dim3((cnt + 3) / 4), dim3(256), 0, stream, cnt,
+                       m->d_level_rows + r0, m->d_diag_slot, m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd,
+                       M, ctx->d_status);
+    IEDG_LAUNCH_CHECK(ctx, "ilu0 small level launch");
+  }
+  return IEDG_OK;
+}
+
 template <typename T, int NB>
 static iedg_status factor_levels_nb(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
   const size_t smem = FactorSmem<T, NB>::bytes;
@@ -567,6 +736,17 @@ static iedg_status factor_levels_nb(iedg_context ctx, iedg_mesh m, T* M, hipStre
 
 template <typename T>
 static iedg_status factor_levels(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
+  switch (m->b) {
+    case 1: return factor_levels_small<T, 1>(ctx, m, M, stream);
+    case 2: return factor_levels_small<T, 2>(ctx, m, M, stream);
+    case 3: return factor_levels_small<T, 3>(ctx, m, M, stream);
+    case 4: return factor_levels_small<T, 4>(ctx, m, M, stream);
+    case 5: return factor_levels_small<T, 5>(ctx, m, M, stream);
+    case 6: return factor_levels_small<T, 6>(ctx, m, M, stream);
+    case 7: return factor_levels_small<T, 7>(ctx, m, M, stream);
+    case 8: return factor_levels_small<T, 8>(ctx, m, M, stream);
+    default: break;
+  }
   switch ((m->b + 15) / 16) {
     case 1: return factor_levels_nb<T, 1>(ctx, m, M, stream);
     case 2: return factor_levels_nb<T, 2>(ctx, m, M, stream);

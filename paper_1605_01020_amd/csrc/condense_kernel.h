@@ -26,6 +26,7 @@
 //        -- MFMA tiles of 64 x 256; the triangular solve with L_pp^{-1} is a
 //        second MFMA pass on the accumulators (each wave owns whole columns)
 //   4. Schur block: M[n:, n:] = in - L21 U12 (MFMA, K = n)
+#include <algorithm>
 #include <climits>
 
 #include "common.h"
@@ -87,13 +88,32 @@ __device__ __attribute__((always_inline)) inline int wave_min(int v) {
 }
 
 
-constexpr int CT = 64;        // panel width
 constexpr int NT = 512;       // threads per workgroup (8 waves)
 static_assert(NT == 512, "default_leaf_width counts rows per thread for 512 threads");
 constexpr int NW = NT / 64;   // waves
 constexpr int SWMAX = 16;     // widest sub-panel (LDS sizing)
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
-constexpr int LIS = CT + 1;   // LDS stride of L^{-1}
+// Panel width CT: 128 columns in FP32 storage, 64 in FP64 (whose panel
+// buffers would not fit the LDS at 128); LIS = CT + 1, the LDS stride of
+// L^{-1}.  Wider panels halve the re-reads of the L and U operands that the
+// Crout updates stream from HBM.
+template <typename T>
+constexpr int CTW = sizeof(T) == 4 ? 128 : 64;
+template <typename T>
+constexpr int LISW = CTW<T> + 1;
+
+// Tile shapes of the GEMM phases (rows x columns): panel columns CM x CT,
+// panel rows CT x 256 (waves stacked along columns: the triangular solve on
+// the accumulators needs all CT rows in each wave; split into 64-row halves
+// the U operand would be read twice), Schur block SM x SN.  FP32: 128 x 128,
+// 128 x 256, 128 x 128; FP64: 256 x 64, 64 x 256, 256 x 64.
+template <typename T>
+struct Shapes {
+  static constexpr bool F32 = sizeof(T) == 4;
+  static constexpr int CM = F32 ? 128 : 256;
+  static constexpr int RN = 256;
+  static constexpr int SM = F32 ? 128 : 256, SN = F32 ? 128 : 64;
+};
 
 
 
@@ -187,13 +207,15 @@ template <> struct Pair<float> { typedef float2 v; };
 // ---- GEMM engine ----------------------------------------------------------
 // acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
 // tile (in = the bordered matrix's input values); rows >= rlim, cols >= clim
-// and k >= K read as zero.  Waves are stacked
-// along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
-// wave 64 x 32).  k-slabs of KC are staged in two LDS buffers; each thread
+// and k >= K read as zero.  Waves are stacked along rows (256 x 64: each
+// wave 32 x 64; 128 x 128: 16 x 128) or, with COLS (the default for wide
+// tiles), along columns (64 x 256: 64 x 32; 128 x 128: 128 x 16).  k-slabs of KC are staged in two LDS buffers; each thread
 // keeps two slabs of global loads in flight.
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, bool COLS = (TM < TN)>
 struct Tile {
-  static constexpr int WR = TM >= TN ? NW : 1;
+  // COLS: waves stacked along columns, each holding every row of its
+  // columns (needed by the panel-row triangular solve); else along rows
+  static constexpr int WR = COLS ? 1 : NW;
   static constexpr int WC = NW / WR;
   static constexpr int WM = TM / WR, WN = TN / WC;
   static constexpr int RB = WM / 16, CB = WN / 16;
@@ -202,7 +224,7 @@ struct Tile {
   static constexpr int STAGE = KC * (SA + SB);
   static constexpr int AL = TM * KC / 2 / NT;   // pair loads per thread per slab
   static constexpr int BL = TN * KC / 2 / NT;
-  static_assert(AL >= 1 && BL >= 1 && RB * CB == 8, "tile shape");
+  static_assert(AL >= 1 && BL >= 1 && (RB * CB == 8 || RB * CB == 16), "tile shape");
 };
 
 // Per-thread global-load descriptors of one k-slab (compile-time counts).
@@ -211,9 +233,9 @@ struct Tile {
 // flight and the wait before storing a slab covers only that slab's loads:
 // the next slab's loads stay in flight behind the MFMA work.  HASW: the
 // tile includes the right-hand-side column (w, FP64 storage).
-template <typename T, int TM, int TN, bool HASW>
+template <typename T, int TM, int TN, bool HASW, bool COLS = (TM < TN)>
 struct SlabLoader {
-  typedef Tile<T, TM, TN> TL;
+  typedef Tile<T, TM, TN, COLS> TL;
   typedef typename Pair<T>::v P2;
   const T* aptr[TL::AL];
   int ak[TL::AL], arow[TL::AL];
@@ -313,10 +335,10 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 // accumulation, v_mfma_f32_16x16x16_bf16 (A operand: lane l holds
 // A[l % 16][4 (l / 16) + i], B operand: B[4 (l / 16) + i][l % 16], i < 4;
 // accumulator as for the FP32 16x16x4 operation).
-template <typename T, int TM, int TN, int MM>
+template <typename T, int TM, int TN, int MM, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, int wr0, int wc0,
-                                typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
-  typedef Tile<T, TM, TN> TL;
+                                typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB]) {
+  typedef Tile<T, TM, TN, COLS> TL;
   typedef Mfma<T> MF;
   const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
   if constexpr (MM == 0) {
@@ -361,17 +383,16 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
 // acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
 // tile; rows >= rlim, cols >= clim and k >= K read as zero.  The accumulators
 // start from the input values (read while the first slabs are in flight) and
-// L enters the MFMAs negated.  Waves are stacked
-// along rows (TM = 256, each wave 32 x 64) or along columns (TN = 256, each
-// wave 64 x 32).  k-slabs of KC go through two LDS stages; each thread keeps
+// L enters the MFMAs negated.  Waves are stacked as described for Tile.
+// k-slabs of KC go through two LDS stages; each thread keeps
 // the global loads of the next two slabs in flight in two register buffers.
 // Accumulators initialised with the tile's input values (zero outside
 // rlim x clim).  SEG >= 0: every column of the tile lies in that segment, so
 // each row is resolved once.
-template <typename T, int TM, int TN, int SEG>
+template <typename T, int TM, int TN, int SEG, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void tile_inputs(const Elem<T>& el, int r0, int rlim, int c0, int clim,
-                                                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
-  typedef Tile<T, TM, TN> TL;
+                                                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB]) {
+  typedef Tile<T, TM, TN, COLS> TL;
   typedef Mfma<T> MF;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
@@ -399,10 +420,10 @@ __device__ __attribute__((always_inline)) inline void tile_inputs(const Elem<T>&
 }
 
 // Store this wave's accumulators inside rlim x clim; SEG as above.
-template <typename T, int TM, int TN, int SEG>
+template <typename T, int TM, int TN, int SEG, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void tile_store(const Elem<T>& el, int r0, int rlim, int c0, int clim,
-                                                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB]) {
-  typedef Tile<T, TM, TN> TL;
+                                                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB]) {
+  typedef Tile<T, TM, TN, COLS> TL;
   typedef Mfma<T> MF;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
@@ -433,21 +454,21 @@ __device__ __attribute__((always_inline)) inline void tile_store(const Elem<T>& 
 
 // seg: the column segment every column of the tile lies in (0 or 1), or -1
 // (uniform across the workgroup, so the branch costs nothing per element)
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void tile_inputs_seg(const Elem<T>& el, int r0, int rlim, int c0, int clim,
-                                                                      typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                                                      typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
                                                                       int seg) {
-  if (seg == 0) tile_inputs<T, TM, TN, 0>(el, r0, rlim, c0, clim, acc);
-  else if (seg == 1) tile_inputs<T, TM, TN, 1>(el, r0, rlim, c0, clim, acc);
-  else tile_inputs<T, TM, TN, -1>(el, r0, rlim, c0, clim, acc);
+  if (seg == 0) tile_inputs<T, TM, TN, 0, COLS>(el, r0, rlim, c0, clim, acc);
+  else if (seg == 1) tile_inputs<T, TM, TN, 1, COLS>(el, r0, rlim, c0, clim, acc);
+  else tile_inputs<T, TM, TN, -1, COLS>(el, r0, rlim, c0, clim, acc);
 }
-template <typename T, int TM, int TN>
+template <typename T, int TM, int TN, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void tile_store_seg(const Elem<T>& el, int r0, int rlim, int c0, int clim,
-                                                                     typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                                                     typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
                                                                      int seg) {
-  if (seg == 0) tile_store<T, TM, TN, 0>(el, r0, rlim, c0, clim, acc);
-  else if (seg == 1) tile_store<T, TM, TN, 1>(el, r0, rlim, c0, clim, acc);
-  else tile_store<T, TM, TN, -1>(el, r0, rlim, c0, clim, acc);
+  if (seg == 0) tile_store<T, TM, TN, 0, COLS>(el, r0, rlim, c0, clim, acc);
+  else if (seg == 1) tile_store<T, TM, TN, 1, COLS>(el, r0, rlim, c0, clim, acc);
+  else tile_store<T, TM, TN, -1, COLS>(el, r0, rlim, c0, clim, acc);
 }
 // The column segment of tile columns [j0, jl): 0, 1, or -1 when it straddles
 // n or holds the right-hand-side column.
@@ -457,22 +478,22 @@ __device__ __attribute__((always_inline)) inline int tile_seg(int j0, int jl, in
 
 // The slab loop is unrolled by two so that stage and buffer indices are
 // compile-time constants.
-template <typename T, int TM, int TN, int MM = 0, bool HASW = false>
+template <typename T, int TM, int TN, int MM = 0, bool HASW = false, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
-                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+                                 typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
                                  int seg = -1) {
-  typedef Tile<T, TM, TN> TL;
+  typedef Tile<T, TM, TN, COLS> TL;
   typedef Mfma<T> MF;
   typedef typename Pair<T>::v P2;
   const int wv = threadIdx.x >> 6;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
   const int lane = threadIdx.x & 63;
   if (K <= 0) {
-    tile_inputs_seg<T, TM, TN>(el, r0, rlim, c0, clim, acc, seg);
+    tile_inputs_seg<T, TM, TN, COLS>(el, r0, rlim, c0, clim, acc, seg);
     return;
   }
   const int nch = (K + KC - 1) / KC;
-  SlabLoader<T, TM, TN, HASW> ld;
+  SlabLoader<T, TM, TN, HASW, COLS> ld;
   ld.init(el, r0, rlim, c0, clim, K);
   T* S0 = smem;
   T* S1 = smem + TL::STAGE;
@@ -484,29 +505,29 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   ld.load(0, a0, b0, w0);
   ld.load(1, a1, b1, w1);
   // the tile's input values, read while the first slabs are in flight
-  tile_inputs_seg<T, TM, TN>(el, r0, rlim, c0, clim, acc, seg);
+  tile_inputs_seg<T, TM, TN, COLS>(el, r0, rlim, c0, clim, acc, seg);
   ld.store(0, S0, a0, b0, w0);
   ld.load(2, a0, b0, w0);
   __syncthreads();
   for (int ch = 0; ch < nch; ch += 2) {
     ld.store(ch + 1, S1, a1, b1, w1);
     ld.load(ch + 3, a1, b1, w1);
-    slab_mma<T, TM, TN, MM>(S0, wr0, wc0, acc);
+    slab_mma<T, TM, TN, MM, COLS>(S0, wr0, wc0, acc);
     __syncthreads();
     if (ch + 1 < nch) {
       ld.store(ch + 2, S0, a0, b0, w0);
       ld.load(ch + 4, a0, b0, w0);
-      slab_mma<T, TM, TN, MM>(S1, wr0, wc0, acc);
+      slab_mma<T, TM, TN, MM, COLS>(S1, wr0, wc0, acc);
       __syncthreads();
     }
   }
 }
 
 // Visit this wave's accumulator elements as (row, col) of the tile.
-template <typename T, int TM, int TN, typename F>
-__device__ __attribute__((always_inline)) inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+template <typename T, int TM, int TN, bool COLS = (TM < TN), typename F = int>
+__device__ __attribute__((always_inline)) inline void for_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
                                F f) {
-  typedef Tile<T, TM, TN> TL;
+  typedef Tile<T, TM, TN, COLS> TL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
 #pragma unroll
@@ -519,10 +540,10 @@ __device__ __attribute__((always_inline)) inline void for_acc(int r0, int c0, ty
 }
 
 // acc element v = f(row, col, value) over this wave's accumulators.
-template <typename T, int TM, int TN, typename F>
-__device__ __attribute__((always_inline)) inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN>::RB][Tile<T, TM, TN>::CB],
+template <typename T, int TM, int TN, bool COLS = (TM < TN), typename F = int>
+__device__ __attribute__((always_inline)) inline void map_acc(int r0, int c0, typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
                                F f) {
-  typedef Tile<T, TM, TN> TL;
+  typedef Tile<T, TM, TN, COLS> TL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wr0 = (wv % TL::WR) * TL::WM, wc0 = (wv / TL::WR) * TL::WN;
 #pragma unroll
@@ -675,7 +696,7 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       for (int o = tid; o < kp * SW; o += NT) {
         const int i = o / SW, j = o % SW;
         T acc = T(0);
-        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * LIS + m] * pb.Xu[m * SW + j];
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * LISW<T> + m] * pb.Xu[m * SW + j];
         pb.Ut[o] = acc;
       }
       __syncthreads();
@@ -902,14 +923,14 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
     if (tid >= kp && tid < kp + sw) {
       const int i = tid - kp;
 #pragma unroll
-      for (int j = 0; j < SW; ++j) pb.Lb[i * CT + kp + j] = (j < i) ? x[0][j] : T(0);
+      for (int j = 0; j < SW; ++j) pb.Lb[i * CTW<T> + kp + j] = (j < i) ? x[0][j] : T(0);
     }
     __syncthreads();
     // their L in the panel's earlier columns: Lb[:, 0:kp] (written by earlier
     // sub-panels, visible since the barrier at the top of this one)
     for (int o = tid; o < sw * kp; o += NT) {
       const int i = o / kp, k = o % kp;
-      pb.Lb[i * CT + k] = el.ld(cs + i, c0 + k);
+      pb.Lb[i * CTW<T> + k] = el.ld(cs + i, c0 + k);
     }
     __syncthreads();
     // (6) grow L_pp^{-1} by rows kp .. kp+sw.  With L = [L11 0; L21 L22]:
@@ -919,8 +940,8 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       for (int o = tid; o < sw * kp; o += NT) {
         const int i = o / kp, k = o % kp;
         T acc = T(0);
-        for (int m = k; m < kp; ++m) acc += pb.Lb[i * CT + m] * pb.Linv[m * LIS + k];
-        Y[i * CT + k] = acc;
+        for (int m = k; m < kp; ++m) acc += pb.Lb[i * CTW<T> + m] * pb.Linv[m * LISW<T> + k];
+        Y[i * CTW<T> + k] = acc;
       }
       __syncthreads();
       if (tid < sw) {
@@ -928,17 +949,17 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
         for (int i = 0; i < sw; ++i) {
           T acc = (i == j) ? T(1) : T(0);
           if (i > j)
-            for (int m = j; m < i; ++m) acc -= pb.Lb[i * CT + kp + m] * pb.Linv[(kp + m) * LIS + kp + j];
-          pb.Linv[(kp + i) * LIS + kp + j] = acc;
+            for (int m = j; m < i; ++m) acc -= pb.Lb[i * CTW<T> + kp + m] * pb.Linv[(kp + m) * LISW<T> + kp + j];
+          pb.Linv[(kp + i) * LISW<T> + kp + j] = acc;
         }
-        for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * LIS + kp + j] = T(0);
+        for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * LISW<T> + kp + j] = T(0);
       }
       __syncthreads();
       for (int o = tid; o < sw * kp; o += NT) {
         const int i = o / kp, k = o % kp;
         T acc = T(0);
-        for (int m = 0; m <= i; ++m) acc += pb.Linv[(kp + i) * LIS + kp + m] * Y[m * CT + k];
-        pb.Linv[(kp + i) * LIS + k] = -acc;
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[(kp + i) * LISW<T> + kp + m] * Y[m * CTW<T> + k];
+        pb.Linv[(kp + i) * LISW<T> + k] = -acc;
       }
       __syncthreads();
     }
@@ -949,8 +970,12 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
 // ---- the kernel -------------------------------------------------------------
 template <typename T>
 struct CondenseSmem {
-  static constexpr int GEMM = 2 * (KC * (256 + 1 + 64 + 2));   // elements, both tile shapes
-  static constexpr int PANEL = CT * LIS + 2 * CT * SWMAX + SWMAX * CT + 2 * NW * SWMAX + 2 * SWMAX;
+  // two stages of the largest tile shape used (elements)
+  static constexpr int STAGE_MAX =
+      std::max({Tile<T, Shapes<T>::CM, CTW<T>>::STAGE, Tile<T, CTW<T>, Shapes<T>::RN>::STAGE,
+                Tile<T, Shapes<T>::SM, Shapes<T>::SN>::STAGE});
+  static constexpr int GEMM = 2 * STAGE_MAX;
+  static constexpr int PANEL = CTW<T> * LISW<T> + 2 * CTW<T> * SWMAX + SWMAX * CTW<T> + 2 * NW * SWMAX + 2 * SWMAX;
   static size_t bytes(int n) {
     return sizeof(T) * (GEMM + PANEL) + sizeof(PanelSmem) + 16 + sizeof(int) * n;
   }
@@ -984,10 +1009,10 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
   T* sg = reinterpret_cast<T*>(smem_raw);
   PanelBufs<T> pb;
   pb.Linv = sg + CondenseSmem<T>::GEMM;
-  pb.Xu = pb.Linv + CT * LIS;
-  pb.Ut = pb.Xu + CT * SWMAX;
-  pb.Lb = pb.Ut + CT * SWMAX;
-  pb.cand = pb.Lb + SWMAX * CT;
+  pb.Xu = pb.Linv + CTW<T> * LISW<T>;
+  pb.Ut = pb.Xu + CTW<T> * SWMAX;
+  pb.Lb = pb.Ut + CTW<T> * SWMAX;
+  pb.cand = pb.Lb + SWMAX * CTW<T>;
   pb.krow = pb.cand + 2 * NW * SWMAX;
   pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * SWMAX);
   int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
@@ -1014,15 +1039,17 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     __syncthreads();
   }
 
-  typedef Tile<T, 256, 64> TA;
-  typedef Tile<T, 64, 256> TB;
-  for (int c0 = 0; c0 < n; c0 += CT) {
-    const int c1 = min(c0 + CT, n);
+  typedef Shapes<T> SH;
+  typedef Tile<T, SH::CM, CTW<T>> TA;
+  typedef Tile<T, CTW<T>, SH::RN> TB;
+  typedef Tile<T, SH::SM, SH::SN> TS;
+  for (int c0 = 0; c0 < n; c0 += CTW<T>) {
+    const int c1 = min(c0 + CTW<T>, n);
     // 1. panel column in Crout order
-    for (int r0 = c0; r0 < N; r0 += 256) {
+    for (int r0 = c0; r0 < N; r0 += SH::CM) {
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, 256, 64, MM>(el, r0, N, c0, c1, c0, sg, acc, 0);  // columns < c1 <= n
-      tile_store_seg<T, 256, 64>(el, r0, N, c0, c1, acc, 0);
+      gemm_tile<T, SH::CM, CTW<T>, MM>(el, r0, N, c0, c1, c0, sg, acc, 0);  // columns < c1 <= n
+      tile_store_seg<T, SH::CM, CTW<T>>(el, r0, N, c0, c1, acc, 0);
     }
     sync_global();
     // 2. factor the panel, growing L_pp^{-1}
@@ -1032,21 +1059,21 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     // blocks, so clear the strictly upper part (and the padding of a
     // narrow last panel)
     const int wp = c1 - c0;
-    for (int q = tid; q < CT * CT; q += NT) {
-      const int i = q / CT, k = q % CT;
-      if (i >= wp || k >= wp || k > i) pb.Linv[i * LIS + k] = T(0);
+    for (int q = tid; q < CTW<T> * CTW<T>; q += NT) {
+      const int i = q / CTW<T>, k = q % CTW<T>;
+      if (i >= wp || k >= wp || k > i) pb.Linv[i * LISW<T> + k] = T(0);
     }
     __syncthreads();
-    // 3. panel row with the triangular solve on the accumulators
-    for (int j0 = c1; j0 < NC; j0 += 256) {
-      const int jl = min(j0 + 256, NC);
+    // 3. panel rows with the triangular solve on the accumulators
+    for (int j0 = c1; j0 < NC; j0 += SH::RN) {
+      const int jl = min(j0 + SH::RN, NC);
       typename MF::acc_t acc[TB::RB][TB::CB];
       const int seg = tile_seg(j0, jl, n, N);
       if (jl > N)  // this tile holds the right-hand-side column
-        gemm_tile<T, 64, 256, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
+        gemm_tile<T, CTW<T>, SH::RN, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
       else
-        gemm_tile<T, 64, 256, MM, false>(el, c0, c1, j0, jl, c0, sg, acc, seg);
-      map_acc<T, 64, 256>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
+        gemm_tile<T, CTW<T>, SH::RN, MM, false>(el, c0, c1, j0, jl, c0, sg, acc, seg);
+      map_acc<T, CTW<T>, SH::RN>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? v : T(0);
       });
       {
@@ -1060,7 +1087,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
           for (int rb = 0; rb <= ib; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const T av = pb.Linv[(16 * ib + li) * LIS + 16 * rb + MF::row(lane, v)];
+              const T av = pb.Linv[(16 * ib + li) * LISW<T> + 16 * rb + MF::row(lane, v)];
 #pragma unroll
               for (int cb = 0; cb < TB::CB; ++cb) nacc[cb] = MF::mac(av, acc[rb][cb][v], nacc[cb]);
             }
@@ -1068,21 +1095,21 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
           for (int cb = 0; cb < TB::CB; ++cb) acc[ib][cb] = nacc[cb];
         }
       }
-      tile_store_seg<T, 64, 256>(el, c0, c1, j0, jl, acc, seg);
+      tile_store_seg<T, CTW<T>, SH::RN>(el, c0, c1, j0, jl, acc, seg);
     }
     sync_global();
   }
   // 4. Schur block
-  for (int r0 = n; r0 < N; r0 += 256) {
-    for (int j0 = n; j0 < NC; j0 += 64) {
-      const int jl = min(j0 + 64, NC);
-      typename MF::acc_t acc[TA::RB][TA::CB];
+  for (int r0 = n; r0 < N; r0 += SH::SM) {
+    for (int j0 = n; j0 < NC; j0 += SH::SN) {
+      const int jl = min(j0 + SH::SN, NC);
+      typename MF::acc_t acc[TS::RB][TS::CB];
       const int seg = tile_seg(j0, jl, n, N);  // 1, or -1 with the right-hand side
       if (jl > N)
-        gemm_tile<T, 256, 64, MM, true>(el, r0, N, j0, jl, n, sg, acc);
+        gemm_tile<T, SH::SM, SH::SN, MM, true>(el, r0, N, j0, jl, n, sg, acc);
       else
-        gemm_tile<T, 256, 64, MM, false>(el, r0, N, j0, jl, n, sg, acc, seg);
-      tile_store_seg<T, 256, 64>(el, r0, N, j0, jl, acc, seg);
+        gemm_tile<T, SH::SM, SH::SN, MM, false>(el, r0, N, j0, jl, n, sg, acc, seg);
+      tile_store_seg<T, SH::SM, SH::SN>(el, r0, N, j0, jl, acc, seg);
     }
   }
   for (int i = tid; i < n; i += NT) a.perm[(size_t)e * n + i] = sperm[i];

@@ -207,6 +207,15 @@ void iedg_batch_destroy(iedg_batch batch);
  * else 8. */
 iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int32_t n_local,
                                 int32_t leaf_width);
+/* Panel width of the condensation's Crout factorisation (section 2.2.1,
+ * eq. LS): 64 or 128 columns for FP32 storage (IEDG_F32, IEDG_BF16), 64
+ * only for IEDG_F64 (IEDG_ERR_INVALID_ARG otherwise), for elements with n
+ * local dofs, kept in the context beside the sub-panel width.  Wider
+ * panels read the L and U operands of the Crout updates half as often;
+ * narrow elements factor faster in narrow panels.  Untuned: 128 for FP32
+ * storage with n >= 1024, else 64. */
+iedg_status iedg_set_panel_width(iedg_context ctx, iedg_prec prec, int32_t n_local,
+                                 int32_t panel_width);
 
 /* ---- a2: assembly of K and R (section 2.2.1, eq. LS) ------------------ */
 /* Kbsr = sum_e P_e^T Ke_e P_e in the BSR layout of `mesh` (storage in

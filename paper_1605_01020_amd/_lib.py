@@ -74,6 +74,7 @@ SIGNATURES = {
                                 P, P, ctypes.POINTER(MrInfo), P]),
     "iedg_batch_destroy": (None, [P]),
     "iedg_set_leaf_width": (c_int32, [P, c_int32, c_int32, c_int32]),
+    "iedg_set_panel_width": (c_int32, [P, c_int32, c_int32, c_int32]),
     "iedg_condense_rhs": (c_int32, [P, c_int32, c_int32, c_int32, c_int32, P, P, P, P, P, P, P]),
     "iedg_assemble": (c_int32, [P, P, c_int32, P, P, P, P, P, P]),
     "iedg_factor_ilu0": (c_int32, [P, P, c_int32, P, P, P]),

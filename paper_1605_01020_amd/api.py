@@ -220,6 +220,11 @@ def set_leaf_width(ctx, n_local, leaf_width, prec=F32):
     ctx.check(ctx.L.iedg_set_leaf_width(ctx.h, int(prec), int(n_local), int(leaf_width)))
 
 
+def set_panel_width(ctx, n_local, panel_width, prec=F32):
+    """Panel width (64, or 128 in FP32 storage) of the condensation for (prec, n)."""
+    ctx.check(ctx.L.iedg_set_panel_width(ctx.h, int(prec), int(n_local), int(panel_width)))
+
+
 class GmresState:
     """GMRES workspace of one mesh (iedg_gmres_state_*), allocated once.
     gmres_solve(..., state=) runs restarted GMRES in it; enqueue() runs one

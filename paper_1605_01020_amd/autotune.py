@@ -1,10 +1,12 @@
-"""Measured choice of the condensation kernel's sub-panel width.
+"""Measured choice of the condensation kernel's sub-panel and panel widths.
 
 The panel factorisation of the condensation kernel keeps sub-panels of 8
-or 16 columns in registers.  For each precision and element size the tuner
-times both on a device-generated sample of elements and keeps the faster;
-the table is stored as tuning.json beside this file and applied with
-iedg_set_leaf_width.
+or 16 columns in registers, and its Crout updates work on panels of 64 or
+(FP32 storage only) 128 columns, which set the GEMM tile shapes.  For each
+precision and element size the tuner times every combination on a
+device-generated sample of elements and keeps the fastest; the table is
+stored as tuning.json beside this file and applied with iedg_set_leaf_width
+and iedg_set_panel_width.
 
     python -m paper_1605_01020_amd.autotune          # measure and write
 """
@@ -15,6 +17,7 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(_HERE, "tuning.json")
 LEAF_CHOICES = (8, 16)
+PANEL_CHOICES = {"f32": (64, 128), "f64": (64,)}
 
 
 def _time_condense(ctx, spec, d, prec, reps):
@@ -48,17 +51,20 @@ def tune(ctx, ps=(2, 3, 4), precs=None, n_elem=512, reps=3, seed=1605010203, log
         for prec in precs:
             best = None
             times = {}
-            for lw in LEAF_CHOICES:
-                api.set_leaf_width(ctx, spec.n, lw, prec=prec)
-                ms = _time_condense(ctx, spec, d, prec, reps)
-                times[lw] = ms
-                log(f"p={p} n={spec.n} prec={'f64' if prec == F64 else 'f32'} sub-panel {lw}: "
-                    f"{ms:.2f} ms for {n_elem} elements")
-                if best is None or ms < times[best]:
-                    best = lw
-            api.set_leaf_width(ctx, spec.n, best, prec=prec)
-            table["entries"].append({"p": p, "n": spec.n, "prec": "f64" if prec == F64 else "f32",
-                                     "leaf_width": best, "ms": {str(k): v for k, v in times.items()}})
+            pn = "f64" if prec == F64 else "f32"
+            for ct in PANEL_CHOICES[pn]:
+                api.set_panel_width(ctx, spec.n, ct, prec=prec)
+                for lw in LEAF_CHOICES:
+                    api.set_leaf_width(ctx, spec.n, lw, prec=prec)
+                    ms = _time_condense(ctx, spec, d, prec, reps)
+                    times[(lw, ct)] = ms
+                    log(f"p={p} n={spec.n} prec={pn} sub-panel {lw} panel {ct}: {ms:.2f} ms for {n_elem} elements")
+                    if best is None or ms < times[best]:
+                        best = (lw, ct)
+            api.set_leaf_width(ctx, spec.n, best[0], prec=prec)
+            api.set_panel_width(ctx, spec.n, best[1], prec=prec)
+            table["entries"].append({"p": p, "n": spec.n, "prec": pn, "leaf_width": best[0], "panel_width": best[1],
+                                     "ms": {f"{k[0]}/{k[1]}": v for k, v in times.items()}})
         del d
         torch.cuda.empty_cache()
     return table
@@ -73,7 +79,10 @@ def apply_tuning(ctx, path=TUNING_PATH):
         table = json.load(f)
     from ._lib import F32, F64
     for e in table.get("entries", []):
-        api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]), prec=F64 if e.get("prec") == "f64" else F32)
+        prec = F64 if e.get("prec") == "f64" else F32
+        api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]), prec=prec)
+        if "panel_width" in e:
+            api.set_panel_width(ctx, int(e["n"]), int(e["panel_width"]), prec=prec)
     return table
 
 

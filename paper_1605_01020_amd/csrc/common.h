@@ -152,8 +152,9 @@ struct iedg_context_s {
   iedg::DeviceStatus* d_status = nullptr;   // device
   iedg::DeviceStatus* h_status = nullptr;   // pinned host mirror
   double* h_scalars = nullptr;              // pinned host readback area
-  // condensation sub-panel widths by (precision, n), set by the autotuner
-  struct LeafChoice { int prec, n, lw; };
+  // condensation sub-panel and panel widths by (precision, n), set by the
+  // autotuner (0: the untuned default)
+  struct LeafChoice { int prec, n, lw, ct; };
   std::vector<LeafChoice> leaf;
   std::mutex leaf_mu;
 };

@@ -14,6 +14,7 @@ struct CondenseArgs {
   double *w, *r;
   DeviceStatus* status;
   int lw;  // sub-panel width (8 or 16) of this segment in the batched form
+  int ct;  // panel width (64 or 128) of this segment in the batched form
 };
 
 // The persistent batched form: n_wg workgroups take n_items (segment,
@@ -26,15 +27,16 @@ struct QueueLaunch {
 };
 
 // One condensation launch.  segs == nullptr: elements 0 .. a.E-1 of `a`, one
-// workgroup each, sub-panel width lw (8 or 16; 0 for the untuned default).
-// Otherwise the batched form over segs as described by q (a, lw unused).
-// Each is defined in the translation unit of its precision.
+// workgroup each, sub-panel width lw (8 or 16) and panel width ct (64, or
+// 128 in FP32 storage), 0 for the untuned defaults.  Otherwise the batched
+// form over segs as described by q (a, lw, ct unused).  Each is defined in
+// the translation unit of its precision.
 hipError_t condense_launch_f64(const CondenseArgs<double>& a, const CondenseArgs<double>* segs, const QueueLaunch& q,
-                               int lw, hipStream_t s);
+                               int lw, int ct, hipStream_t s);
 hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q,
-                               int lw, hipStream_t s);
+                               int lw, int ct, hipStream_t s);
 hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q,
-                                int lw, hipStream_t s);
+                                int lw, int ct, hipStream_t s);
 
 // Persistent grid size of the batched form for LDS sized for n_max local
 // dofs (0 on a HIP error), per precision.
@@ -51,6 +53,11 @@ inline int default_leaf_width(size_t elem_bytes, int n, int t) {
   const int q = (qa <= 1 && qc <= 1) ? 2 : (qa <= 3 && qc <= 1) ? 4 : 7;
   return (elem_bytes == 8 ? q <= 2 : q <= 4) ? 16 : 8;
 }
+
+// Untuned panel width: 128 columns for FP32 storage and elements of at
+// least 1024 local dofs (measured: 128 wins at n = 1280 and 2500, loses at
+// 540), else 64 (the only width FP64 storage is built for).
+inline int default_panel_width(size_t elem_bytes, int n) { return elem_bytes == 4 && n >= 1024 ? 128 : 64; }
 
 // Largest n and t the kernel is built for (rows per thread: 5 of A, 2 of C).
 constexpr int kCondenseMaxN = 5 * 512, kCondenseMaxT = 2 * 512;

@@ -83,17 +83,25 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
   }
 }
 
-// The context's sub-panel width for (prec, n); BF16 without an entry of its
-// own takes the FP32 entry; 0 (the kernel's default) when untuned.
-static int leaf_width(iedg_context ctx, iedg_prec prec, int n) {
+// The context's sub-panel width (field lw) or panel width (field ct) for
+// (prec, n); BF16 without an entry of its own takes the FP32 entry; 0 (the
+// kernel's default) when untuned.
+static int tuned(iedg_context ctx, iedg_prec prec, int n, int iedg_context_s::LeafChoice::*field) {
   std::lock_guard<std::mutex> lock(ctx->leaf_mu);
   int fallback = 0;
   for (const auto& c : ctx->leaf) {
     if (c.n != n) continue;
-    if (c.prec == (int)prec) return c.lw;
-    if (prec == IEDG_BF16 && c.prec == (int)IEDG_F32) fallback = c.lw;
+    if (c.prec == (int)prec && c.*field) return c.*field;
+    if (prec == IEDG_BF16 && c.prec == (int)IEDG_F32) fallback = c.*field;
   }
   return fallback;
+}
+static int leaf_width(iedg_context ctx, iedg_prec prec, int n) {
+  return tuned(ctx, prec, n, &iedg_context_s::LeafChoice::lw);
+}
+static int panel_width(iedg_context ctx, iedg_prec prec, int n) {
+  const int ct = tuned(ctx, prec, n, &iedg_context_s::LeafChoice::ct);
+  return prec == IEDG_F64 ? 64 : ct;  // FP64 storage is built for 64 only
 }
 
 }  // namespace iedg
@@ -132,13 +140,13 @@ extern "C" iedg_status iedg_condense(iedg_context ctx, int32_t n_elem, int32_t n
   if (prec == IEDG_F64) {
     CondenseArgs<double> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
                            (double*)LU, (double*)U12, (double*)L21, (double*)Ke, perm, w, r, ctx->d_status, 0};
-    err = condense_launch_f64(a, nullptr, QueueLaunch{}, leaf_width(ctx, prec, n_local), stream);
+    err = condense_launch_f64(a, nullptr, QueueLaunch{}, leaf_width(ctx, prec, n_local), 64, stream);
   } else if (prec == IEDG_F32 || prec == IEDG_BF16) {
     CondenseArgs<float> a{n_elem, n_local, n_trace_elem, A, B, C, D, F,
                           (float*)LU, (float*)U12, (float*)L21, (float*)Ke, perm, w, r, ctx->d_status, 0};
-    const int lw = leaf_width(ctx, prec, n_local);
-    err = prec == IEDG_F32 ? condense_launch_f32(a, nullptr, QueueLaunch{}, lw, stream)
-                           : condense_launch_bf16(a, nullptr, QueueLaunch{}, lw, stream);
+    const int lw = leaf_width(ctx, prec, n_local), ct = panel_width(ctx, prec, n_local);
+    err = prec == IEDG_F32 ? condense_launch_f32(a, nullptr, QueueLaunch{}, lw, ct, stream)
+                           : condense_launch_bf16(a, nullptr, QueueLaunch{}, lw, ct, stream);
   } else {
     return set_error(ctx, IEDG_ERR_UNSUPPORTED, "condense: precision %d not built", (int)prec);
   }
@@ -207,13 +215,14 @@ extern "C" iedg_status iedg_batch_create_sized(iedg_context ctx, int32_t n_seg, 
     if (!aligned16({g.A, g.B, g.C, g.D, g.F, g.LU, g.perm, g.U12, g.L21, g.w, g.Ke, g.r}))
       return set_error(ctx, IEDG_ERR_INVALID_ARG, "batch_create: segment %d arrays must be 16-byte aligned", s);
     // the width iedg_condense would use for this size now (context table or default)
-    int lw = leaf_width(ctx, prec, n);
+    int lw = leaf_width(ctx, prec, n), ct = panel_width(ctx, prec, n);
     if (lw == 0) lw = default_leaf_width(prec == IEDG_F64 ? 8 : 4, n, t);
+    if (ct == 0) ct = default_panel_width(prec == IEDG_F64 ? 8 : 4, n);
     if (g.n_elem > 0) n_max = std::max(n_max, n);
     a64.push_back(CondenseArgs<double>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (double*)g.LU, (double*)g.U12,
-                                       (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw});
+                                       (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw, ct});
     a32.push_back(CondenseArgs<float>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (float*)g.LU, (float*)g.U12,
-                                      (float*)g.L21, (float*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw});
+                                      (float*)g.L21, (float*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw, ct});
   }
   // Work list: size classes from the largest element down (the long items
   // start first, the persistent workgroups finish on short ones); within a
@@ -281,11 +290,11 @@ extern "C" iedg_status iedg_condense_batched(iedg_context ctx, iedg_batch b, hip
   const QueueLaunch q{b->d_items, b->n_items, b->n_max, b->n_wg, b->d_counter};
   hipError_t err;
   if (b->prec == IEDG_F64)
-    err = condense_launch_f64(CondenseArgs<double>{}, (const CondenseArgs<double>*)b->d_segs, q, 0, stream);
+    err = condense_launch_f64(CondenseArgs<double>{}, (const CondenseArgs<double>*)b->d_segs, q, 0, 0, stream);
   else if (b->prec == IEDG_BF16)
-    err = condense_launch_bf16(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, stream);
+    err = condense_launch_bf16(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, 0, stream);
   else
-    err = condense_launch_f32(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, stream);
+    err = condense_launch_f32(CondenseArgs<float>{}, (const CondenseArgs<float>*)b->d_segs, q, 0, 0, stream);
   if (err != hipSuccess) return hip_check(ctx, err, "condense_batched launch");
   return IEDG_OK;
 }
@@ -309,6 +318,21 @@ extern "C" iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int
       c.lw = leaf_width;
       return IEDG_OK;
     }
-  ctx->leaf.push_back({(int)prec, n_local, leaf_width});
+  ctx->leaf.push_back({(int)prec, n_local, leaf_width, 0});
+  return IEDG_OK;
+}
+
+extern "C" iedg_status iedg_set_panel_width(iedg_context ctx, iedg_prec prec, int32_t n_local, int32_t panel_width) {
+  if (!ctx) return IEDG_ERR_INVALID_ARG;
+  if (n_local <= 0 || (prec != IEDG_F32 && prec != IEDG_BF16 && prec != IEDG_F64) ||
+      (panel_width != 64 && panel_width != 128) || (prec == IEDG_F64 && panel_width != 64))
+    return set_error(ctx, IEDG_ERR_INVALID_ARG, "set_panel_width: 64 or 128 (FP32/BF16 storage), 64 (FP64)");
+  std::lock_guard<std::mutex> lock(ctx->leaf_mu);
+  for (auto& c : ctx->leaf)
+    if (c.prec == (int)prec && c.n == n_local) {
+      c.ct = panel_width;
+      return IEDG_OK;
+    }
+  ctx->leaf.push_back({(int)prec, n_local, 0, panel_width});
   return IEDG_OK;
 }

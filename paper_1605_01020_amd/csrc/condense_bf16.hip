@@ -3,9 +3,9 @@
 
 namespace iedg {
 
-hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw,
+hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw, int ct,
                                 hipStream_t s) {
-  return dispatch_condense<float, 1>(a, s, lw, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
+  return dispatch_condense<float, 1>(a, s, lw, ct, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
 }
 
 int condense_queue_slots_bf16(int n_max) { return queue_slots<float, 1>(n_max); }

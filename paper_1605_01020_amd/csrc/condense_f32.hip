@@ -3,9 +3,9 @@
 
 namespace iedg {
 
-hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw,
+hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q, int lw, int ct,
                                hipStream_t s) {
-  return dispatch_condense<float, 0>(a, s, lw, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
+  return dispatch_condense<float, 0>(a, s, lw, ct, segs, q.items, q.n_items, q.n_max, q.counter, q.n_wg);
 }
 
 int condense_queue_slots_f32(int n_max) { return queue_slots<float, 0>(n_max); }

@@ -93,27 +93,27 @@ static_assert(NT == 512, "default_leaf_width counts rows per thread for 512 thre
 constexpr int NW = NT / 64;   // waves
 constexpr int SWMAX = 16;     // widest sub-panel (LDS sizing)
 constexpr int KC = 16;        // k-slab depth of the GEMM engine
-// Panel width CT: 128 columns in FP32 storage, 64 in FP64 (whose panel
-// buffers would not fit the LDS at 128); LIS = CT + 1, the LDS stride of
-// L^{-1}.  Wider panels halve the re-reads of the L and U operands that the
-// Crout updates stream from HBM.
-template <typename T>
-constexpr int CTW = sizeof(T) == 4 ? 128 : 64;
-template <typename T>
-constexpr int LISW = CTW<T> + 1;
-
-// Tile shapes of the GEMM phases (rows x columns): panel columns CM x CT,
-// panel rows CT x 256 (waves stacked along columns: the triangular solve on
-// the accumulators needs all CT rows in each wave; split into 64-row halves
-// the U operand would be read twice), Schur block SM x SN.  FP32: 128 x 128,
-// 128 x 256, 128 x 128; FP64: 256 x 64, 64 x 256, 256 x 64.
-template <typename T>
+// Panel width CT (64 or 128 columns; 128 only in FP32 storage, whose panel
+// buffers fit the LDS at that width) with the tile shapes of the GEMM phases
+// (rows x columns): panel columns CM x CT, panel rows CT x RN (waves stacked
+// along columns: the triangular solve on the accumulators needs all CT rows
+// in each wave), Schur block SM x SN.  CT = 64: 256 x 64, 64 x 256, 256 x 64;
+// CT = 128: 128 x 128, 128 x 256, 128 x 128.  Wider panels halve the
+// re-reads of the L and U operands that the Crout updates stream from HBM;
+// narrow elements factor faster in narrow panels (the width is tuned per
+// element size).
+template <typename T, int CT>
 struct Shapes {
-  static constexpr bool F32 = sizeof(T) == 4;
-  static constexpr int CM = F32 ? 128 : 256;
+  static_assert(CT == 64 || (CT == 128 && sizeof(T) == 4), "panel width");
+  static constexpr int LIS = CT + 1;  // LDS stride of L^{-1}
+  static constexpr bool W = CT == 128;
+  static constexpr int CM = W ? 128 : 256;
   static constexpr int RN = 256;
-  static constexpr int SM = F32 ? 128 : 256, SN = F32 ? 128 : 64;
+  static constexpr int SM = W ? 128 : 256, SN = W ? 128 : 64;
 };
+// The widest panel a precision is built for.
+template <typename T>
+constexpr int CT_MAX = sizeof(T) == 4 ? 128 : 64;
 
 
 
@@ -622,7 +622,7 @@ __device__ __attribute__((always_inline)) inline void store_row16(T* dst, const 
   for (int j = 0; j < W; ++j) d[j] = src[j];
 }
 
-template <typename T, int QA, int QC, int SW>
+template <typename T, int QA, int QC, int SW, int CT>
 __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, int* sperm, int c0, int c1,
                                                             const PanelBufs<T>& pb, DeviceStatus* status, int elem) {
   typedef PanelShape<T, QA, QC, SW> PS;
@@ -696,7 +696,7 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       for (int o = tid; o < kp * SW; o += NT) {
         const int i = o / SW, j = o % SW;
         T acc = T(0);
-        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * LISW<T> + m] * pb.Xu[m * SW + j];
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * (CT + 1) + m] * pb.Xu[m * SW + j];
         pb.Ut[o] = acc;
       }
       __syncthreads();
@@ -923,14 +923,14 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
     if (tid >= kp && tid < kp + sw) {
       const int i = tid - kp;
 #pragma unroll
-      for (int j = 0; j < SW; ++j) pb.Lb[i * CTW<T> + kp + j] = (j < i) ? x[0][j] : T(0);
+      for (int j = 0; j < SW; ++j) pb.Lb[i * CT + kp + j] = (j < i) ? x[0][j] : T(0);
     }
     __syncthreads();
     // their L in the panel's earlier columns: Lb[:, 0:kp] (written by earlier
     // sub-panels, visible since the barrier at the top of this one)
     for (int o = tid; o < sw * kp; o += NT) {
       const int i = o / kp, k = o % kp;
-      pb.Lb[i * CTW<T> + k] = el.ld(cs + i, c0 + k);
+      pb.Lb[i * CT + k] = el.ld(cs + i, c0 + k);
     }
     __syncthreads();
     // (6) grow L_pp^{-1} by rows kp .. kp+sw.  With L = [L11 0; L21 L22]:
@@ -940,8 +940,8 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
       for (int o = tid; o < sw * kp; o += NT) {
         const int i = o / kp, k = o % kp;
         T acc = T(0);
-        for (int m = k; m < kp; ++m) acc += pb.Lb[i * CTW<T> + m] * pb.Linv[m * LISW<T> + k];
-        Y[i * CTW<T> + k] = acc;
+        for (int m = k; m < kp; ++m) acc += pb.Lb[i * CT + m] * pb.Linv[m * (CT + 1) + k];
+        Y[i * CT + k] = acc;
       }
       __syncthreads();
       if (tid < sw) {
@@ -949,17 +949,17 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
         for (int i = 0; i < sw; ++i) {
           T acc = (i == j) ? T(1) : T(0);
           if (i > j)
-            for (int m = j; m < i; ++m) acc -= pb.Lb[i * CTW<T> + kp + m] * pb.Linv[(kp + m) * LISW<T> + kp + j];
-          pb.Linv[(kp + i) * LISW<T> + kp + j] = acc;
+            for (int m = j; m < i; ++m) acc -= pb.Lb[i * CT + kp + m] * pb.Linv[(kp + m) * (CT + 1) + kp + j];
+          pb.Linv[(kp + i) * (CT + 1) + kp + j] = acc;
         }
-        for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * LISW<T> + kp + j] = T(0);
+        for (int i = 0; i < j; ++i) pb.Linv[(kp + i) * (CT + 1) + kp + j] = T(0);
       }
       __syncthreads();
       for (int o = tid; o < sw * kp; o += NT) {
         const int i = o / kp, k = o % kp;
         T acc = T(0);
-        for (int m = 0; m <= i; ++m) acc += pb.Linv[(kp + i) * LISW<T> + kp + m] * Y[m * CTW<T> + k];
-        pb.Linv[(kp + i) * LISW<T> + k] = -acc;
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[(kp + i) * (CT + 1) + kp + m] * Y[m * CT + k];
+        pb.Linv[(kp + i) * (CT + 1) + k] = -acc;
       }
       __syncthreads();
     }
@@ -968,14 +968,14 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
 }
 
 // ---- the kernel -------------------------------------------------------------
-template <typename T>
+template <typename T, int CT>
 struct CondenseSmem {
   // two stages of the largest tile shape used (elements)
   static constexpr int STAGE_MAX =
-      std::max({Tile<T, Shapes<T>::CM, CTW<T>>::STAGE, Tile<T, CTW<T>, Shapes<T>::RN>::STAGE,
-                Tile<T, Shapes<T>::SM, Shapes<T>::SN>::STAGE});
+      std::max({Tile<T, Shapes<T, CT>::CM, CT>::STAGE, Tile<T, CT, Shapes<T, CT>::RN>::STAGE,
+                Tile<T, Shapes<T, CT>::SM, Shapes<T, CT>::SN>::STAGE});
   static constexpr int GEMM = 2 * STAGE_MAX;
-  static constexpr int PANEL = CTW<T> * LISW<T> + 2 * CTW<T> * SWMAX + SWMAX * CTW<T> + 2 * NW * SWMAX + 2 * SWMAX;
+  static constexpr int PANEL = CT * (CT + 1) + 2 * CT * SWMAX + SWMAX * CT + 2 * NW * SWMAX + 2 * SWMAX;
   static size_t bytes(int n) {
     return sizeof(T) * (GEMM + PANEL) + sizeof(PanelSmem) + 16 + sizeof(int) * n;
   }
@@ -1001,18 +1001,18 @@ __device__ __attribute__((always_inline)) inline void convert_copy(const double*
   }
 }
 
-template <typename T, int QA, int QC, int LW, int MM>
+template <typename T, int QA, int QC, int LW, int MM, int CT>
 __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T>& a, int e, unsigned char* smem_raw) {
   typedef Mfma<T> MF;
   const int tid = threadIdx.x;
   const int n = a.n, t = a.t, N = n + t;
   T* sg = reinterpret_cast<T*>(smem_raw);
   PanelBufs<T> pb;
-  pb.Linv = sg + CondenseSmem<T>::GEMM;
-  pb.Xu = pb.Linv + CTW<T> * LISW<T>;
-  pb.Ut = pb.Xu + CTW<T> * SWMAX;
-  pb.Lb = pb.Ut + CTW<T> * SWMAX;
-  pb.cand = pb.Lb + SWMAX * CTW<T>;
+  pb.Linv = sg + CondenseSmem<T, CT>::GEMM;
+  pb.Xu = pb.Linv + CT * (CT + 1);
+  pb.Ut = pb.Xu + CT * SWMAX;
+  pb.Lb = pb.Ut + CT * SWMAX;
+  pb.cand = pb.Lb + SWMAX * CT;
   pb.krow = pb.cand + 2 * NW * SWMAX;
   pb.ps = reinterpret_cast<PanelSmem*>(pb.krow + 2 * SWMAX);
   int* sperm = reinterpret_cast<int*>(reinterpret_cast<unsigned char*>(pb.ps) + sizeof(PanelSmem) + 16);
@@ -1039,29 +1039,29 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
     __syncthreads();
   }
 
-  typedef Shapes<T> SH;
-  typedef Tile<T, SH::CM, CTW<T>> TA;
-  typedef Tile<T, CTW<T>, SH::RN> TB;
+  typedef Shapes<T, CT> SH;
+  typedef Tile<T, SH::CM, CT> TA;
+  typedef Tile<T, CT, SH::RN> TB;
   typedef Tile<T, SH::SM, SH::SN> TS;
-  for (int c0 = 0; c0 < n; c0 += CTW<T>) {
-    const int c1 = min(c0 + CTW<T>, n);
+  for (int c0 = 0; c0 < n; c0 += CT) {
+    const int c1 = min(c0 + CT, n);
     // 1. panel column in Crout order
     for (int r0 = c0; r0 < N; r0 += SH::CM) {
       typename MF::acc_t acc[TA::RB][TA::CB];
-      gemm_tile<T, SH::CM, CTW<T>, MM>(el, r0, N, c0, c1, c0, sg, acc, 0);  // columns < c1 <= n
-      tile_store_seg<T, SH::CM, CTW<T>>(el, r0, N, c0, c1, acc, 0);
+      gemm_tile<T, SH::CM, CT, MM>(el, r0, N, c0, c1, c0, sg, acc, 0);  // columns < c1 <= n
+      tile_store_seg<T, SH::CM, CT>(el, r0, N, c0, c1, acc, 0);
     }
     sync_global();
     // 2. factor the panel, growing L_pp^{-1}
-    panel_factor<T, QA, QC, LW>(el, sperm, c0, c1, pb, a.status, e);
+    panel_factor<T, QA, QC, LW, CT>(el, sperm, c0, c1, pb, a.status, e);
     // the leaves write L_pp^{-1} on and below the diagonal of each 8-row
     // strip only; the triangular solve below reads whole 16 x 16 diagonal
     // blocks, so clear the strictly upper part (and the padding of a
     // narrow last panel)
     const int wp = c1 - c0;
-    for (int q = tid; q < CTW<T> * CTW<T>; q += NT) {
-      const int i = q / CTW<T>, k = q % CTW<T>;
-      if (i >= wp || k >= wp || k > i) pb.Linv[i * LISW<T> + k] = T(0);
+    for (int q = tid; q < CT * CT; q += NT) {
+      const int i = q / CT, k = q % CT;
+      if (i >= wp || k >= wp || k > i) pb.Linv[i * (CT + 1) + k] = T(0);
     }
     __syncthreads();
     // 3. panel rows with the triangular solve on the accumulators
@@ -1070,10 +1070,10 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
       typename MF::acc_t acc[TB::RB][TB::CB];
       const int seg = tile_seg(j0, jl, n, N);
       if (jl > N)  // this tile holds the right-hand-side column
-        gemm_tile<T, CTW<T>, SH::RN, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
+        gemm_tile<T, CT, SH::RN, MM, true>(el, c0, c1, j0, jl, c0, sg, acc);
       else
-        gemm_tile<T, CTW<T>, SH::RN, MM, false>(el, c0, c1, j0, jl, c0, sg, acc, seg);
-      map_acc<T, CTW<T>, SH::RN>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
+        gemm_tile<T, CT, SH::RN, MM, false>(el, c0, c1, j0, jl, c0, sg, acc, seg);
+      map_acc<T, CT, SH::RN>(c0, j0, acc, [&](int row, int col, T v) __attribute__((always_inline)) -> T {
         return (row < c1 && col < jl) ? v : T(0);
       });
       {
@@ -1087,7 +1087,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
           for (int rb = 0; rb <= ib; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const T av = pb.Linv[(16 * ib + li) * LISW<T> + 16 * rb + MF::row(lane, v)];
+              const T av = pb.Linv[(16 * ib + li) * (CT + 1) + 16 * rb + MF::row(lane, v)];
 #pragma unroll
               for (int cb = 0; cb < TB::CB; ++cb) nacc[cb] = MF::mac(av, acc[rb][cb][v], nacc[cb]);
             }
@@ -1095,7 +1095,7 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
           for (int cb = 0; cb < TB::CB; ++cb) acc[ib][cb] = nacc[cb];
         }
       }
-      tile_store_seg<T, CTW<T>, SH::RN>(el, c0, c1, j0, jl, acc, seg);
+      tile_store_seg<T, CT, SH::RN>(el, c0, c1, j0, jl, acc, seg);
     }
     sync_global();
   }
@@ -1117,10 +1117,10 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
 }
 
 // One element per workgroup.
-template <typename T, int QA, int QC, int LW, int MM>
+template <typename T, int QA, int QC, int LW, int MM, int CT>
 __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  condense_one<T, QA, QC, LW, MM>(a, blockIdx.x, smem_raw);
+  condense_one<T, QA, QC, LW, MM, CT>(a, blockIdx.x, smem_raw);
 }
 
 // One item of the batched form, compiled as a function of its own so that
@@ -1130,7 +1130,7 @@ __global__ __launch_bounds__(NT) void condense_kernel(CondenseArgs<T> a) {
 // itself and reads the segment through the constant address space: the
 // segment's sizes and pointers then sit in scalar registers as they do in
 // the one-element-per-workgroup kernel.
-template <typename T, int QA, int QC, int LW, int MM>
+template <typename T, int QA, int QC, int LW, int MM, int CT>
 __device__ __noinline__ void condense_item(const CondenseArgs<T>* segs, int seg, int e) {
 #if defined(__HIP_DEVICE_COMPILE__)  // address spaces exist only in the device pass
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1139,14 +1139,29 @@ __device__ __noinline__ void condense_item(const CondenseArgs<T>* segs, int seg,
   const uint64_t pu = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)p) |
                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(p >> 32)) << 32);
   const CondenseArgs<T> a = ((ConstArgs*)pu)[__builtin_amdgcn_readfirstlane(seg)];
-  condense_one<T, QA, QC, LW, MM>(a, __builtin_amdgcn_readfirstlane(e), smem_raw);
+  condense_one<T, QA, QC, LW, MM, CT>(a, __builtin_amdgcn_readfirstlane(e), smem_raw);
 #endif
+}
+
+// The instantiation of one item's size class, sub-panel width and panel width.
+template <typename T, int MM, int CT>
+__device__ __forceinline__ void queue_item(const CondenseArgs<T>* segs, int seg, int e, int qa, int qc, int lw) {
+  if (qa <= 1 && qc <= 1) {
+    if (lw == 16) condense_item<T, 1, 1, 16, MM, CT>(segs, seg, e);
+    else condense_item<T, 1, 1, 8, MM, CT>(segs, seg, e);
+  } else if (qa <= 3 && qc <= 1) {
+    if (lw == 16) condense_item<T, 3, 1, 16, MM, CT>(segs, seg, e);
+    else condense_item<T, 3, 1, 8, MM, CT>(segs, seg, e);
+  } else {
+    if (lw == 16) condense_item<T, 5, 2, 16, MM, CT>(segs, seg, e);
+    else condense_item<T, 5, 2, 8, MM, CT>(segs, seg, e);
+  }
 }
 
 // Batched form, persistent: n_wg workgroups take (segment, element) items
 // from a queue (one atomic counter) until it runs dry.  Segments may differ
 // in element size: each item runs the instantiation of its size class and of
-// its segment's sub-panel width (a.lw), so it computes exactly what the
+// its segment's sub-panel and panel widths (a.lw, a.ct), so it computes exactly what the
 // one-element-per-workgroup kernel computes for it (bitwise).  The work list
 // is ordered largest elements first, so the last items taken are short ones.
 template <typename T, int MM>
@@ -1164,18 +1179,15 @@ __global__ __launch_bounds__(NT) void condense_queue_kernel(const CondenseArgs<T
     if (it >= n_items) break;
     const int2 w = items[it];
     const int seg = __builtin_amdgcn_readfirstlane(w.x), e = __builtin_amdgcn_readfirstlane(w.y);
-    const int n = segs[seg].n, t = segs[seg].t, lw = segs[seg].lw;
+    const int n = segs[seg].n, t = segs[seg].t, lw = segs[seg].lw, ct = segs[seg].ct;
     const int qa = (n + NT - 1) / NT, qc = (t + NT - 1) / NT;
-    if (qa <= 1 && qc <= 1) {
-      if (lw == 16) condense_item<T, 1, 1, 16, MM>(segs, seg, e);
-      else condense_item<T, 1, 1, 8, MM>(segs, seg, e);
-    } else if (qa <= 3 && qc <= 1) {
-      if (lw == 16) condense_item<T, 3, 1, 16, MM>(segs, seg, e);
-      else condense_item<T, 3, 1, 8, MM>(segs, seg, e);
-    } else {
-      if (lw == 16) condense_item<T, 5, 2, 16, MM>(segs, seg, e);
-      else condense_item<T, 5, 2, 8, MM>(segs, seg, e);
+    if constexpr (CT_MAX<T> == 128) {
+      if (ct == 128) {
+        queue_item<T, MM, 128>(segs, seg, e, qa, qc, lw);
+        continue;
+      }
     }
+    queue_item<T, MM, 64>(segs, seg, e, qa, qc, lw);
   }
 }
 
@@ -1187,10 +1199,10 @@ __global__ void condense_queue_reset_kernel(int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
-template <typename T, int QA, int QC, int LW, int MM>
+template <typename T, int QA, int QC, int LW, int MM, int CT>
 hipError_t launch_condense_lw(const CondenseArgs<T>& a, hipStream_t s) {
-  const size_t smem = CondenseSmem<T>::bytes(a.n);
-  auto kern = condense_kernel<T, QA, QC, LW, MM>;
+  const size_t smem = CondenseSmem<T, CT>::bytes(a.n);
+  auto kern = condense_kernel<T, QA, QC, LW, MM, CT>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
@@ -1198,20 +1210,30 @@ hipError_t launch_condense_lw(const CondenseArgs<T>& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename T, int QA, int QC, int MM>
+template <typename T, int QA, int QC, int MM, int CT>
 hipError_t launch_condense(const CondenseArgs<T>& a, int lw, hipStream_t s) {
-  if (lw == 16) return launch_condense_lw<T, QA, QC, 16, MM>(a, s);
-  return launch_condense_lw<T, QA, QC, 8, MM>(a, s);
+  if (lw == 16) return launch_condense_lw<T, QA, QC, 16, MM, CT>(a, s);
+  return launch_condense_lw<T, QA, QC, 8, MM, CT>(a, s);
+}
+
+template <typename T, int MM, int CT>
+hipError_t launch_class(const CondenseArgs<T>& a, int lw, hipStream_t s) {
+  const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
+  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1, MM, CT>(a, lw, s);
+  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1, MM, CT>(a, lw, s);
+  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, MM, CT>(a, lw, s);
+  return hipErrorInvalidValue;
 }
 
 // Workgroups of the batched form that fit on the device at once (the
-// persistent grid) when LDS is sized for n_max local dofs.
+// persistent grid) when LDS is sized for n_max local dofs at the widest
+// panel.
 template <typename T, int MM>
 int queue_slots(int n_max) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t smem = CondenseSmem<T>::bytes(n_max);
+  const size_t smem = CondenseSmem<T, CT_MAX<T>>::bytes(n_max);
   auto kern = condense_queue_kernel<T, MM>;
   if (hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)smem) != hipSuccess)
@@ -1221,12 +1243,13 @@ int queue_slots(int n_max) {
 }
 
 // Every instantiation of one precision (and operand mode); each precision
-// is compiled in a translation unit of its own.
+// is compiled in a translation unit of its own.  lw, ct: sub-panel width (8
+// or 16) and panel width (64 or 128), 0 for the untuned defaults.
 template <typename T, int MM>
-hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, const CondenseArgs<T>* segs,
+hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, int ct, const CondenseArgs<T>* segs,
                              const int2* items, int n_items, int n_max, int* counter, int n_wg) {
   if (segs) {
-    const size_t smem = CondenseSmem<T>::bytes(n_max);
+    const size_t smem = CondenseSmem<T, CT_MAX<T>>::bytes(n_max);
     auto kern = condense_queue_kernel<T, MM>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -1235,12 +1258,12 @@ hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, co
     hipLaunchKernelGGL(kern, dim3(n_wg), dim3(NT), smem, s, segs, items, n_items, counter);
     return hipGetLastError();
   }
-  const int qa = (a.n + NT - 1) / NT, qc = (a.t + NT - 1) / NT;
   if (lw == 0) lw = default_leaf_width(sizeof(T), a.n, a.t);
-  if (qa <= 1 && qc <= 1) return launch_condense<T, 1, 1, MM>(a, lw, s);
-  if (qa <= 3 && qc <= 1) return launch_condense<T, 3, 1, MM>(a, lw, s);
-  if (qa <= 5 && qc <= 2) return launch_condense<T, 5, 2, MM>(a, lw, s);
-  return hipErrorInvalidValue;
+  if (ct == 0) ct = default_panel_width(sizeof(T), a.n);
+  if constexpr (CT_MAX<T> == 128) {
+    if (ct == 128) return launch_class<T, MM, 128>(a, lw, s);
+  }
+  return launch_class<T, MM, 64>(a, lw, s);
 }
 
 }  // namespace iedg

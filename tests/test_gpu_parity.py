@@ -467,18 +467,23 @@ def test_ilu0_singular_pivot_block_reported(ctx):
     ctx.sync_status()  # cleared
 
 
+@pytest.mark.parametrize("p", [2, 4])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_condense_largest_elements(ctx, prec):
-    """p = 4 elements (n = 2,500, t = 750: five A rows and two C rows per
-    thread, 40 panels with a 4-wide last one) in every precision, with both
-    sub-panel widths."""
+def test_condense_widths(ctx, p, prec):
+    """Every sub-panel width, and every panel width the precision is built
+    for (64 and 128 columns in FP32 storage, 64 in FP64), against the
+    oracle: p = 2 (n = 540, a narrow last panel at either width) and p = 4
+    (n = 2,500, t = 750: five A rows and two C rows per thread; 40 panels of
+    64 with a 4-wide last one, or 20 of 128 with a 68-wide last one)."""
     from paper_1605_01020_amd import F64, F32, BF16
-    m, spec, blocks, G = host_case((2, 1, 1), 4, seed=SEED_BASE + 9)
+    m, spec, blocks, G = host_case((2, 1, 1), p, seed=SEED_BASE + 9)
     d = host_blocks_to_dev(blocks)
     refs = [oracle.condense_element(b_["A"], b_["B"], b_["C"], b_["D"], b_["F"]) for b_ in blocks]
-    for lw in (8, 16):
-        api.set_leaf_width(ctx, spec.n, lw, prec=F64 if prec == 0 else F32)
-        _say(f"condense p=4 prec={prec} sub-panel {lw}")
+    tp = F64 if prec == 0 else F32
+    for lw, ct in [(lw, ct) for lw in (8, 16) for ct in ((64,) if prec == 0 else (64, 128))]:
+        api.set_leaf_width(ctx, spec.n, lw, prec=tp)
+        api.set_panel_width(ctx, spec.n, ct, prec=tp)
+        _say(f"condense p={p} prec={prec} sub-panel {lw} panel {ct}")
         fac = api.condense(ctx, d["A"], d["B"], d["C"], d["D"], d["F"], prec=prec)
         ctx.sync_status()
         for e, (Ke, re, _) in enumerate(refs):
@@ -526,8 +531,10 @@ def test_argument_errors(ctx):
                            None, p(z), None, s0) == -1
     assert L.iedg_condense(ctx.h, 1, 8, 4, F64, z8, p(z), p(z), p(z), None, p(z), p(i32), p(z), p(z),
                            None, p(z), None, s0) == -1
-    # sub-panel width, GMRES restart and state size
+    # sub-panel and panel widths, GMRES restart and state size
     assert L.iedg_set_leaf_width(ctx.h, F64, 1280, 4) == -1
+    assert L.iedg_set_panel_width(ctx.h, F64, 1280, 128) == -1
+    assert L.iedg_set_panel_width(ctx.h, F64, 1280, 96) == -1
     m, spec, blocks, G = host_case((1, 1, 1), 1)
     mesh = _mesh(ctx, m, spec)
     h = ctypes.c_void_p()

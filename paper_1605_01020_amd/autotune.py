@@ -17,7 +17,8 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(_HERE, "tuning.json")
 LEAF_CHOICES = (8, 16)
-PANEL_CHOICES = {"f32": (64, 128), "f64": (64,)}
+PANEL_CHOICES = {"f32": (64, 128), "bf16": (64, 128), "f64": (64,)}
+PREC_NAME = {0: "f64", 1: "f32", 2: "bf16"}
 
 
 def _time_condense(ctx, spec, d, prec, reps):
@@ -40,10 +41,10 @@ def _time_condense(ctx, spec, d, prec, reps):
 def tune(ctx, ps=(2, 3, 4), precs=None, n_elem=512, reps=3, seed=1605010203, log=print):
     import torch
     from . import api
-    from ._lib import F32, F64
+    from ._lib import F32, F64, BF16
     from synth import ElementSpec
     import synth.device as sd
-    precs = (F32, F64) if precs is None else precs
+    precs = (F32, F64, BF16) if precs is None else precs
     table = {"n_elem": n_elem, "entries": []}
     for p in ps:
         spec = ElementSpec(p)
@@ -51,7 +52,7 @@ def tune(ctx, ps=(2, 3, 4), precs=None, n_elem=512, reps=3, seed=1605010203, log
         for prec in precs:
             best = None
             times = {}
-            pn = "f64" if prec == F64 else "f32"
+            pn = PREC_NAME[int(prec)]
             for ct in PANEL_CHOICES[pn]:
                 api.set_panel_width(ctx, spec.n, ct, prec=prec)
                 for lw in LEAF_CHOICES:
@@ -77,9 +78,9 @@ def apply_tuning(ctx, path=TUNING_PATH):
         return None
     with open(path) as f:
         table = json.load(f)
-    from ._lib import F32, F64
+    from ._lib import F32, F64, BF16
     for e in table.get("entries", []):
-        prec = F64 if e.get("prec") == "f64" else F32
+        prec = {"f64": F64, "bf16": BF16}.get(e.get("prec"), F32)
         api.set_leaf_width(ctx, int(e["n"]), int(e["leaf_width"]), prec=prec)
         if "panel_width" in e:
             api.set_panel_width(ctx, int(e["n"]), int(e["panel_width"]), prec=prec)

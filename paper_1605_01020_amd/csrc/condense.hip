@@ -84,23 +84,26 @@ __global__ __launch_bounds__(RTHR) void condense_rhs_kernel(int n, int t, const 
 }
 
 // The context's sub-panel width (field lw) or panel width (field ct) for
-// (prec, n); BF16 without an entry of its own takes the FP32 entry; 0 (the
-// kernel's default) when untuned.
-static int tuned(iedg_context ctx, iedg_prec prec, int n, int iedg_context_s::LeafChoice::*field) {
+// (prec, n); with bf16_from_f32, BF16 without an entry of its own takes the
+// FP32 entry; 0 (the kernel's default) when untuned.
+static int tuned(iedg_context ctx, iedg_prec prec, int n, int iedg_context_s::LeafChoice::*field,
+                 bool bf16_from_f32) {
   std::lock_guard<std::mutex> lock(ctx->leaf_mu);
   int fallback = 0;
   for (const auto& c : ctx->leaf) {
     if (c.n != n) continue;
     if (c.prec == (int)prec && c.*field) return c.*field;
-    if (prec == IEDG_BF16 && c.prec == (int)IEDG_F32) fallback = c.*field;
+    if (bf16_from_f32 && prec == IEDG_BF16 && c.prec == (int)IEDG_F32) fallback = c.*field;
   }
   return fallback;
 }
 static int leaf_width(iedg_context ctx, iedg_prec prec, int n) {
-  return tuned(ctx, prec, n, &iedg_context_s::LeafChoice::lw);
+  return tuned(ctx, prec, n, &iedg_context_s::LeafChoice::lw, true);
 }
+// The panel width is not taken over from FP32: BF16 operands favour other
+// widths (the operands are rounded on every fragment read).
 static int panel_width(iedg_context ctx, iedg_prec prec, int n) {
-  const int ct = tuned(ctx, prec, n, &iedg_context_s::LeafChoice::ct);
+  const int ct = tuned(ctx, prec, n, &iedg_context_s::LeafChoice::ct, false);
   return prec == IEDG_F64 ? 64 : ct;  // FP64 storage is built for 64 only
 }
 
@@ -217,7 +220,7 @@ extern "C" iedg_status iedg_batch_create_sized(iedg_context ctx, int32_t n_seg, 
     // the width iedg_condense would use for this size now (context table or default)
     int lw = leaf_width(ctx, prec, n), ct = panel_width(ctx, prec, n);
     if (lw == 0) lw = default_leaf_width(prec == IEDG_F64 ? 8 : 4, n, t);
-    if (ct == 0) ct = default_panel_width(prec == IEDG_F64 ? 8 : 4, n);
+    if (ct == 0) ct = default_panel_width(prec == IEDG_F64 ? 8 : 4, n, prec == IEDG_BF16 ? 1 : 0);
     if (g.n_elem > 0) n_max = std::max(n_max, n);
     a64.push_back(CondenseArgs<double>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (double*)g.LU, (double*)g.U12,
                                        (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw, ct});

@@ -1259,7 +1259,7 @@ hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, in
     return hipGetLastError();
   }
   if (lw == 0) lw = default_leaf_width(sizeof(T), a.n, a.t);
-  if (ct == 0) ct = default_panel_width(sizeof(T), a.n);
+  if (ct == 0) ct = default_panel_width(sizeof(T), a.n, MM);
   if constexpr (CT_MAX<T> == 128) {
     if (ct == 128) return launch_class<T, MM, 128>(a, lw, s);
   }

@@ -129,18 +129,17 @@ __device__ inline void wave_dot_rows(const T* const (&rows)[R], const double* ve
   for (int r = 0; r < R; ++r) out[r] = wave_sum(s[r]);
 }
 
-// Device status word: first failing index (element or block row) + code.
+// Device status word: the smallest failing index (element or block row)
+// and its code in one 64-bit word, (index << 8) | -code, all ones when
+// clear, so that one atomicMin keeps an index with its own code whatever
+// the order in which failures arrive.
 struct DeviceStatus {
-  int32_t code;   // 0 = ok, otherwise an iedg_status value
-  int32_t pad;
-  int64_t index;  // smallest failing index seen
+  unsigned long long word;
 };
+constexpr unsigned long long kStatusClear = ~0ull;
 
 __device__ inline void latch_status(DeviceStatus* st, int32_t code, int64_t index) {
-  // keep the smallest index: deterministic regardless of scheduling
-  atomicMin(reinterpret_cast<unsigned long long*>(&st->index),
-            static_cast<unsigned long long>(index));
-  atomicExch(&st->code, code);
+  atomicMin(&st->word, (static_cast<unsigned long long>(index) << 8) | static_cast<unsigned long long>(-code & 0xff));
 }
 
 }  // namespace iedg

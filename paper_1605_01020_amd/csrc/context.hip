@@ -144,7 +144,7 @@ iedg_status iedg_create(iedg_context* out, int device) {
   if (e == hipSuccess) e = hipHostMalloc(&ctx->h_status, sizeof(DeviceStatus), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc(&ctx->h_scalars, 4096, hipHostMallocDefault);
   if (e == hipSuccess) {
-    DeviceStatus init{0, 0, INT64_MAX};
+    DeviceStatus init{kStatusClear};
     e = hipMemcpy(ctx->d_status, &init, sizeof(init), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
@@ -174,13 +174,16 @@ iedg_status iedg_sync_status(iedg_context ctx, hipStream_t stream, int64_t* bad_
   if (!ctx) return IEDG_ERR_INVALID_ARG;
   IEDG_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(DeviceStatus), hipMemcpyDeviceToHost, stream));
   IEDG_HIP(ctx, hipStreamSynchronize(stream));
-  DeviceStatus st = *ctx->h_status;
-  if (bad_index) *bad_index = st.code ? st.index : -1;
-  if (st.code) {
-    DeviceStatus init{0, 0, INT64_MAX};
+  const DeviceStatus st = *ctx->h_status;
+  const bool failed = st.word != kStatusClear;
+  const int32_t code = failed ? -static_cast<int32_t>(st.word & 0xff) : 0;
+  const long long index = failed ? static_cast<long long>(st.word >> 8) : -1;
+  if (bad_index) *bad_index = index;
+  if (failed) {
+    DeviceStatus init{kStatusClear};
     IEDG_HIP(ctx, hipMemcpy(ctx->d_status, &init, sizeof(init), hipMemcpyHostToDevice));
-    return set_error(ctx, static_cast<iedg_status>(st.code), "device reported %s at index %lld",
-                     iedg_status_string(static_cast<iedg_status>(st.code)), (long long)st.index);
+    return set_error(ctx, static_cast<iedg_status>(code), "device reported %s at index %lld",
+                     iedg_status_string(static_cast<iedg_status>(code)), index);
   }
   return IEDG_OK;
 }

@@ -39,7 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # the sources of the FP32 condensation kernel (HBM counters are reported only
 # while these are unchanged since the counters were taken)
 CONDENSE_SOURCES = ["paper_1605_01020_amd/csrc/condense_kernel.h", "paper_1605_01020_amd/csrc/condense.h",
-                    "paper_1605_01020_amd/csrc/condense_f32.hip", "paper_1605_01020_amd/csrc/common.h",
+                    "paper_1605_01020_amd/csrc/condense_f32.hip", "paper_1605_01020_amd/csrc/condense_f32_single.hip",
+                    "paper_1605_01020_amd/csrc/common.h",
                     "paper_1605_01020_amd/tuning.json"]
 
 

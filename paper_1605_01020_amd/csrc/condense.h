@@ -38,6 +38,12 @@ hipError_t condense_launch_f32(const CondenseArgs<float>& a, const CondenseArgs<
 hipError_t condense_launch_bf16(const CondenseArgs<float>& a, const CondenseArgs<float>* segs, const QueueLaunch& q,
                                 int lw, int ct, hipStream_t s);
 
+// The one-element-per-workgroup launches, each precision in a translation
+// unit of its own (condense_*_single.hip): lw, ct as above.
+hipError_t condense_single_f64(const CondenseArgs<double>& a, int lw, int ct, hipStream_t s);
+hipError_t condense_single_f32(const CondenseArgs<float>& a, int lw, int ct, hipStream_t s);
+hipError_t condense_single_bf16(const CondenseArgs<float>& a, int lw, int ct, hipStream_t s);
+
 // Persistent grid size of the batched form for LDS sized for n_max local
 // dofs (0 on a HIP error), per precision.
 int condense_queue_slots_f64(int n_max);

@@ -1242,22 +1242,28 @@ int queue_slots(int n_max) {
   return cus * per_cu;
 }
 
-// Every instantiation of one precision (and operand mode); each precision
-// is compiled in a translation unit of its own.  lw, ct: sub-panel width (8
-// or 16) and panel width (64 or 128), 0 for the untuned defaults.
+// The batched form of one precision (and operand mode): every item
+// instantiation lives in the persistent kernel, compiled in the translation
+// unit of its precision.
 template <typename T, int MM>
-hipError_t dispatch_condense(const CondenseArgs<T>& a, hipStream_t s, int lw, int ct, const CondenseArgs<T>* segs,
-                             const int2* items, int n_items, int n_max, int* counter, int n_wg) {
-  if (segs) {
-    const size_t smem = CondenseSmem<T, CT_MAX<T>>::bytes(n_max);
-    auto kern = condense_queue_kernel<T, MM>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(condense_queue_reset_kernel<T>, dim3(1), dim3(64), 0, s, counter);
-    hipLaunchKernelGGL(kern, dim3(n_wg), dim3(NT), smem, s, segs, items, n_items, counter);
-    return hipGetLastError();
-  }
+hipError_t dispatch_queue(hipStream_t s, const CondenseArgs<T>* segs, const int2* items, int n_items, int n_max,
+                          int* counter, int n_wg) {
+  const size_t smem = CondenseSmem<T, CT_MAX<T>>::bytes(n_max);
+  auto kern = condense_queue_kernel<T, MM>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(condense_queue_reset_kernel<T>, dim3(1), dim3(64), 0, s, counter);
+  hipLaunchKernelGGL(kern, dim3(n_wg), dim3(NT), smem, s, segs, items, n_items, counter);
+  return hipGetLastError();
+}
+
+// One launch over elements 0 .. a.E-1 (the one-element-per-workgroup
+// kernels of one precision, compiled in a translation unit of their own so
+// that the two halves of a precision build in parallel).  lw, ct: sub-panel
+// width (8 or 16) and panel width (64 or 128), 0 for the untuned defaults.
+template <typename T, int MM>
+hipError_t dispatch_single(const CondenseArgs<T>& a, hipStream_t s, int lw, int ct) {
   if (lw == 0) lw = default_leaf_width(sizeof(T), a.n, a.t);
   if (ct == 0) ct = default_panel_width(sizeof(T), a.n, MM);
   if constexpr (CT_MAX<T> == 128) {

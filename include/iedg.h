@@ -213,7 +213,8 @@ iedg_status iedg_set_leaf_width(iedg_context ctx, iedg_prec prec, int32_t n_loca
  * local dofs, kept in the context beside the sub-panel width.  Wider
  * panels read the L and U operands of the Crout updates half as often;
  * narrow elements factor faster in narrow panels.  Untuned: 128 for
- * IEDG_F32 with n >= 1024, else 64 (BF16 does not take the FP32 entry). */
+ * IEDG_F32 and IEDG_BF16 with n >= 1024, else 64 (BF16 keeps an entry of
+ * its own and does not take the FP32 one). */
 iedg_status iedg_set_panel_width(iedg_context ctx, iedg_prec prec, int32_t n_local,
                                  int32_t panel_width);
 

@@ -60,12 +60,12 @@ inline int default_leaf_width(size_t elem_bytes, int n, int t) {
   return (elem_bytes == 8 ? q <= 2 : q <= 4) ? 16 : 8;
 }
 
-// Untuned panel width: 128 columns for FP32 storage and elements of at
-// least 1024 local dofs (measured: 128 wins at n = 1280 and 2500, loses at
-// 540), else 64 (the only width FP64 storage is built for).  BF16 operands
-// (mm = 1) default to 64.
-inline int default_panel_width(size_t elem_bytes, int n, int mm = 0) {
-  return elem_bytes == 4 && mm == 0 && n >= 1024 ? 128 : 64;
+// Untuned panel width: 128 columns for FP32 storage (FP32 or BF16
+// operands) and elements of at least 1024 local dofs (measured: 128 wins at
+// n = 1280 and 2500, loses at 540), else 64 (the only width FP64 storage is
+// built for).
+inline int default_panel_width(size_t elem_bytes, int n) {
+  return elem_bytes == 4 && n >= 1024 ? 128 : 64;
 }
 
 // Largest n and t the kernel is built for (rows per thread: 5 of A, 2 of C).

@@ -220,7 +220,7 @@ extern "C" iedg_status iedg_batch_create_sized(iedg_context ctx, int32_t n_seg, 
     // the width iedg_condense would use for this size now (context table or default)
     int lw = leaf_width(ctx, prec, n), ct = panel_width(ctx, prec, n);
     if (lw == 0) lw = default_leaf_width(prec == IEDG_F64 ? 8 : 4, n, t);
-    if (ct == 0) ct = default_panel_width(prec == IEDG_F64 ? 8 : 4, n, prec == IEDG_BF16 ? 1 : 0);
+    if (ct == 0) ct = default_panel_width(prec == IEDG_F64 ? 8 : 4, n);
     if (g.n_elem > 0) n_max = std::max(n_max, n);
     a64.push_back(CondenseArgs<double>{g.n_elem, n, t, g.A, g.B, g.C, g.D, g.F, (double*)g.LU, (double*)g.U12,
                                        (double*)g.L21, (double*)g.Ke, g.perm, g.w, g.r, ctx->d_status, lw, ct});

@@ -98,18 +98,19 @@ constexpr int KC = 16;        // k-slab depth of the GEMM engine
 // (rows x columns): panel columns CM x CT, panel rows CT x RN (waves stacked
 // along columns: the triangular solve on the accumulators needs all CT rows
 // in each wave), Schur block SM x SN.  CT = 64: 256 x 64, 64 x 256, 256 x 64;
-// CT = 128: 128 x 128, 128 x 256, 128 x 128.  Wider panels halve the
-// re-reads of the L and U operands that the Crout updates stream from HBM;
-// narrow elements factor faster in narrow panels (the width is tuned per
-// element size).
+// CT = 128: 256 x 128, 128 x 256, 256 x 128 (64 accumulators a lane in
+// every shape).  Wider panels halve the re-reads of the L and U operands
+// that the Crout updates stream from HBM, and 256-row tiles read the
+// right-hand operand once for 256 rows instead of 128; narrow elements
+// factor faster in narrow panels (the width is tuned per element size).
 template <typename T, int CT>
 struct Shapes {
   static_assert(CT == 64 || (CT == 128 && sizeof(T) == 4), "panel width");
   static constexpr int LIS = CT + 1;  // LDS stride of L^{-1}
   static constexpr bool W = CT == 128;
-  static constexpr int CM = W ? 128 : 256;
+  static constexpr int CM = 256;
   static constexpr int RN = 256;
-  static constexpr int SM = W ? 128 : 256, SN = W ? 128 : 64;
+  static constexpr int SM = 256, SN = W ? 128 : 64;
 };
 // The widest panel a precision is built for.
 template <typename T>
@@ -208,9 +209,10 @@ template <> struct Pair<float> { typedef float2 v; };
 // acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
 // tile (in = the bordered matrix's input values); rows >= rlim, cols >= clim
 // and k >= K read as zero.  Waves are stacked along rows (256 x 64: each
-// wave 32 x 64; 128 x 128: 16 x 128) or, with COLS (the default for wide
-// tiles), along columns (64 x 256: 64 x 32; 128 x 128: 128 x 16).  k-slabs of KC are staged in two LDS buffers; each thread
-// keeps two slabs of global loads in flight.
+// wave 32 x 64; 256 x 128: 32 x 128) or, with COLS (the default for wide
+// tiles), along columns (64 x 256: 64 x 32; 128 x 256: 128 x 32).  k-slabs
+// of KC are staged in two LDS buffers; each thread keeps two slabs of
+// global loads in flight.
 template <typename T, int TM, int TN, bool COLS = (TM < TN)>
 struct Tile {
   // COLS: waves stacked along columns, each holding every row of its
@@ -1265,7 +1267,7 @@ hipError_t dispatch_queue(hipStream_t s, const CondenseArgs<T>* segs, const int2
 template <typename T, int MM>
 hipError_t dispatch_single(const CondenseArgs<T>& a, hipStream_t s, int lw, int ct) {
   if (lw == 0) lw = default_leaf_width(sizeof(T), a.n, a.t);
-  if (ct == 0) ct = default_panel_width(sizeof(T), a.n, MM);
+  if (ct == 0) ct = default_panel_width(sizeof(T), a.n);
   if constexpr (CT_MAX<T> == 128) {
     if (ct == 128) return launch_class<T, MM, 128>(a, lw, s);
   }

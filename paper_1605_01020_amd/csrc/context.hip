@@ -78,6 +78,11 @@ iedg_status build_pattern(iedg_context ctx, iedg_mesh_s* m, const std::vector<st
     std::vector<int> fill(m->level_ptr.begin(), m->level_ptr.end() - 1);
     for (int i = 0; i < NF; ++i) m->level_rows[fill[level[i]]++] = i;
   }
+  m->sweep_fused = nlev > 0;
+  for (int r = nlev > 0 ? m->level_ptr[nlev - 1] : 0; r < NF; ++r) {
+    const int i = m->level_rows[r];
+    if (diag_slot[i] + 1 != m->row_ptr[i + 1]) m->sweep_fused = false;
+  }
   // BILU(0) schedule: for row i, lower slots (i,k) in elimination order; for
   // each, the updates A_ij -= L_ik U_kj over j later than k coupled to both
   std::vector<int32_t> lptr(NF + 1, 0), lslots, uptr(1, 0), upd;

@@ -10,6 +10,10 @@ struct iedg_mesh_s {
   int32_t n_elem = 0, n_face = 0, b = 0, t = 0, slots = 6;
   int64_t n_trace = 0, nnzb = 0;
   int32_t n_levels = 0;
+  // the rows of the last level have no upper slots (true for every
+  // symmetric pattern): the BILU(0) apply then runs that level's forward and
+  // backward steps in one launch
+  bool sweep_fused = false;
   int64_t n_lslots = 0, n_updates = 0;
 
   // host copies (exported by iedg_mesh_query)

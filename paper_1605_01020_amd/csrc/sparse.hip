@@ -156,31 +156,43 @@ __global__ __launch_bounds__(STHR) void spmv_kernel(int b, const int32_t* row_fa
   }
 }
 
-// One level of the BILU(0) sweeps.  Forward (upper = 0): y_i = x_i - sum
-// over lower slots L_ik y_k.  Backward (upper = 1): y_i = Uinv_i (y_i - sum
-// over upper slots U_ij y_j).  x may equal y.
+// One level of the BILU(0) sweeps (rows[n_copy ..] of the launch):
+//   mode 0, forward:           y_i = x_i - sum over lower slots L_ik v_k;
+//   mode 1, backward:          y_i = Uinv_i (y_i - sum over upper slots U_ij v_j);
+//   mode 2, forward + inverse: y_i = Uinv_i (x_i - sum over lower slots L_ik v_k),
+//           for the last level, whose rows have no upper slots;
+// v is y, or x where every summed neighbour lies in level 0 (whose forward
+// values equal x).  The first n_copy workgroups copy y_i = x_i for the rows
+// of level 0, which have no lower slots, so that level 0 and level 1 share a
+// launch.  x may equal y.
 template <typename T>
 __global__ __launch_bounds__(STHR) void sweep_kernel(int b, const int32_t* rows, const int32_t* row_face,
                                                      const int32_t* row_ptr, const int32_t* diag_slot,
                                                      const int32_t* col_face, const T* M, const double* x,
-                                                     double* y, int upper, const int* skip) {
+                                                     double* y, const double* v, int mode, int n_copy,
+                                                     const int* skip) {
   __shared__ double red[STHR + 128];
   if (skip && *skip) return;
   const int i = rows[blockIdx.x];
-  const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
-  const int ds = diag_slot[i];
-  const int s0 = upper ? ds + 1 : row_ptr[i];
-  const int s1 = upper ? row_ptr[i + 1] : ds;
-  const double v = block_row_sum<T>(b, M, col_face, s0, s1, y, g, G, rr);
-  group_reduce(red, b, G, g, rr, v);
   const size_t o = (size_t)row_face[i] * b;
-  if (!upper) {
-    if (threadIdx.x < b) y[o + threadIdx.x] = x[o + threadIdx.x] - red[G * b + threadIdx.x];
+  if ((int)blockIdx.x < n_copy) {
+    if (x != y && threadIdx.x < b) y[o + threadIdx.x] = x[o + threadIdx.x];
     return;
   }
-  // s = x_i - sum  ->  red[0:b]; then y_i = Uinv s
+  const int G = STHR / b, g = threadIdx.x / b, rr = threadIdx.x % b;
+  const int ds = diag_slot[i];
+  const int s0 = mode == 1 ? ds + 1 : row_ptr[i];
+  const int s1 = mode == 1 ? row_ptr[i + 1] : ds;
+  const double* base = mode == 1 ? y : x;
+  const double sum = block_row_sum<T>(b, M, col_face, s0, s1, v, g, G, rr);
+  group_reduce(red, b, G, g, rr, sum);
+  if (mode == 0) {
+    if (threadIdx.x < b) y[o + threadIdx.x] = base[o + threadIdx.x] - red[G * b + threadIdx.x];
+    return;
+  }
+  // s = base_i - sum  ->  svec; then y_i = Uinv s
   __shared__ double svec[128];
-  if (threadIdx.x < b) svec[threadIdx.x] = x[o + threadIdx.x] - red[G * b + threadIdx.x];
+  if (threadIdx.x < b) svec[threadIdx.x] = base[o + threadIdx.x] - red[G * b + threadIdx.x];
   __syncthreads();
   double acc = 0.0;
   if (g < G) {
@@ -526,23 +538,46 @@ iedg_status spmv_launch(iedg_context ctx, iedg_mesh m, iedg_prec kprec, const vo
 }
 
 // y = M^{-1} x : forward sweep over levels, then backward sweep in reverse.
+// With sweep_fused (the last level has no upper slots) level 0's forward
+// step, a copy, shares a launch with level 1, and the last level's forward
+// and backward steps run as one: 2 L - 2 launches for L >= 2 levels instead
+// of 2 L, with bitwise the same result (level 0's forward values are x
+// exactly, and the last level's backward sum is empty).
+template <typename T>
+static void sweep_launch(iedg_mesh m, int l0, int l1, int n_copy, const T* M, const double* x, double* y,
+                         const double* v, int mode, hipStream_t stream, const int* skip) {
+  const int r0 = m->level_ptr[l0], cnt = m->level_ptr[l1] - r0;
+  hipLaunchKernelGGL(sweep_kernel<T>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
+                     m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, M, x, y, v, mode, n_copy, skip);
+}
+
+template <typename T>
+static void ilu0_apply_levels(iedg_mesh m, const T* M, const double* x, double* y, hipStream_t stream,
+                              const int* skip) {
+  const int L = m->n_levels;
+  if (L == 0) return;
+  if (!m->sweep_fused) {
+    for (int l = 0; l < L; ++l) sweep_launch<T>(m, l, l + 1, 0, M, x, y, y, 0, stream, skip);
+    for (int l = L - 1; l >= 0; --l) sweep_launch<T>(m, l, l + 1, 0, M, y, y, y, 1, stream, skip);
+    return;
+  }
+  if (L == 1) {
+    sweep_launch<T>(m, 0, 1, 0, M, x, y, y, 2, stream, skip);
+    return;
+  }
+  // levels 0 and 1: level 1 sums over level-0 neighbours only, read from x
+  const int cnt0 = m->level_ptr[1] - m->level_ptr[0];
+  sweep_launch<T>(m, 0, 2, cnt0, M, x, y, x, L == 2 ? 2 : 0, stream, skip);
+  for (int l = 2; l < L; ++l) sweep_launch<T>(m, l, l + 1, 0, M, x, y, y, l == L - 1 ? 2 : 0, stream, skip);
+  for (int l = L - 2; l >= 0; --l) sweep_launch<T>(m, l, l + 1, 0, M, y, y, y, 1, stream, skip);
+}
+
 iedg_status ilu0_apply_launch(iedg_context ctx, iedg_mesh m, iedg_prec mprec, const void* M, const double* x,
                               double* y, hipStream_t stream, const int* skip) {
-  for (int dir = 0; dir < 2; ++dir) {
-    for (int li = 0; li < m->n_levels; ++li) {
-      const int l = dir == 0 ? li : m->n_levels - 1 - li;
-      const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
-      const double* src = dir == 0 ? x : y;
-      if (mprec == IEDG_F64)
-        hipLaunchKernelGGL(sweep_kernel<double>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
-                           m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const double*)M, src, y,
-                           dir, skip);
-      else
-        hipLaunchKernelGGL(sweep_kernel<float>, dim3(cnt), dim3(STHR), 0, stream, m->b, m->d_level_rows + r0,
-                           m->d_row_face, m->d_row_ptr, m->d_diag_slot, m->d_col_face, (const float*)M, src, y,
-                           dir, skip);
-    }
-  }
+  if (mprec == IEDG_F64)
+    ilu0_apply_levels<double>(m, (const double*)M, x, y, stream, skip);
+  else
+    ilu0_apply_levels<float>(m, (const float*)M, x, y, stream, skip);
   IEDG_LAUNCH_CHECK(ctx, "ilu0 sweep launch");
   return IEDG_OK;
 }

@@ -170,6 +170,60 @@ def test_ilu0_and_products_parity(ctx, ordering):
     assert rel(z, oracle.bilu0_apply(tm, fac, x)) <= 1e-12
 
 
+def _slot_case(case):
+    """(elem_units, n_units, b, ordering, expected level count or None)."""
+    if case == "diagonal":          # every unit alone: one level
+        return [[e] for e in range(7)], 7, 5, "colour", 1
+    if case == "chain_colour":      # a chain of units in two colours
+        return [[e, e + 1] for e in range(9)], 10, 5, "colour", 2
+    if case == "chain_natural":     # the same chain in natural order: ten levels
+        return [[e, e + 1] for e in range(9)], 10, 5, "natural", 10
+    m = StructuredHexMesh(2, 2, 1)  # face-private units, b = 20
+    return m.elem_faces(), m.n_face, 20, "colour", None
+
+
+@pytest.mark.parametrize("case", ["diagonal", "chain_colour", "chain_natural", "faces"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("inplace", [False, True])
+def test_ilu0_apply_level_counts(ctx, case, prec, inplace):
+    """The BILU(0) apply merges level 0's forward copy into level 1's launch
+    and the last level's forward and backward steps into one launch; with
+    1, 2, 6 and 10 levels, in place and not, FP64 and FP32 factor storage, it
+    equals the oracle's two sweeps over the device's own factor blocks."""
+    from paper_1605_01020_amd import F32, F64
+    eu, nu, b, ordering, nlev = _slot_case(case)
+    tm = oracle.TraceMesh(eu, nu, b)
+    mesh = api.Mesh(ctx, eu, nu, b, ordering=ordering, slots=True)
+    if nlev is not None:
+        assert mesh.n_levels == nlev
+    q = mesh.query()
+    rng = np.random.default_rng(17)
+    K = {}
+    for f in range(nu):
+        for g in tm.pattern[f]:
+            K[(f, g)] = rng.standard_normal((b, b)) + (4.0 * b * np.eye(b) if f == g else 0.0)
+    pr, dt = (F64, torch.float64) if prec == "f64" else (F32, torch.float32)
+    _say(f"ilu0 apply {case} {prec} inplace={inplace} levels={mesh.n_levels}")
+    Kd = dev(bsr_from_oracle(mesh, K, q)).to(dt)
+    Md = api.factor_ilu0(ctx, mesh, Kd, prec=pr)
+    ctx.sync_status()
+    got = oracle_from_bsr(mesh, Md.double().cpu().numpy(), q)
+    pos = np.empty(nu, dtype=np.int64)
+    pos[q["order"]] = np.arange(nu)
+    fac = {"order": q["order"], "pos": pos, "L": {}, "U": {}, "Uinv": {}}
+    for (f, g), blk in got.items():
+        if f == g:
+            fac["Uinv"][f] = blk
+        elif pos[g] < pos[f]:
+            fac["L"][(f, g)] = blk
+        else:
+            fac["U"][(f, g)] = blk
+    x = rng.standard_normal(tm.n_trace)
+    xd = dev(x)
+    z = api.ilu0_apply(ctx, mesh, Md, xd, prec=pr, y=xd if inplace else None).cpu().numpy()
+    assert rel(z, oracle.bilu0_apply(tm, fac, x)) <= 1e-13
+
+
 @pytest.mark.parametrize("dims,p", [((2, 2, 2), 1), ((2, 2, 1), 2)])
 def test_full_solve_matches_dense(ctx, dims, p):
     from paper_1605_01020_amd.solver import NewtonStepSolver

@@ -2,8 +2,9 @@
 
 Writes the same seeded element blocks as synth.matrices straight into
 device memory (torch CUDA tensors), so large workloads never pass through
-host memory.  Values agree with the host generator to a few ulps (the
-transcendental functions differ); the Philox words agree bit for bit.
+host memory.  Values agree with the host generator bit for bit (the same
+Philox words, and the same series for ln, cos and sin evaluated in the same
+order).
 """
 import ctypes
 import os

@@ -30,6 +30,57 @@ def test_uniform_endpoints():
     assert u1 == 1.0 and u2 == 1.0 - 2.0 ** -53
 
 
+def test_elementary_functions_of_the_generator():
+    """ln_unit and cos_sin_turns (the generator's own series) against
+    numpy's library functions to a few ulps, exact special values, and
+    constants that are the nearest doubles to their exact values."""
+    import math
+    import re
+    from decimal import Decimal, getcontext
+    from fractions import Fraction
+    from synth import philox as P
+    getcontext().prec = 50
+    ln2 = Decimal(2).ln()
+    assert abs(Decimal(P.LN2) - ln2) <= Decimal(2.0 ** -53) * Decimal(P.LN2) / 2
+    assert P.HALF_PI == math.pi / 2 and P.SQRT_HALF == math.sqrt(0.5)
+    for k, c in enumerate(P.LOG_COEF):
+        assert Fraction(c) == Fraction(float(Fraction(1, 2 * k + 1)))
+        assert abs(Fraction(c) - Fraction(1, 2 * k + 1)) <= Fraction(c) * Fraction(1, 2 ** 53)
+    for k, c in enumerate(P.SIN_COEF):
+        exact = Fraction((-1) ** k, math.factorial(2 * k + 1))
+        assert abs(Fraction(c) - exact) <= abs(exact) * Fraction(1, 2 ** 53)
+    for k, c in enumerate(P.COS_COEF):
+        exact = Fraction((-1) ** k, math.factorial(2 * k))
+        assert abs(Fraction(c) - exact) <= abs(exact) * Fraction(1, 2 ** 53)
+    rng = np.random.default_rng(4)
+    u1 = (rng.integers(0, 2 ** 53, 200_000).astype(np.float64) + 1.0) * 2.0 ** -53
+    ref = np.log(u1)
+    assert np.all(np.abs(P.ln_unit(u1) - ref) <= 4.5e-16 * np.abs(ref) + 1e-300)
+    u2 = rng.integers(0, 2 ** 53, 200_000).astype(np.float64) * 2.0 ** -53
+    c, s = P.cos_sin_turns(u2)
+    assert np.max(np.abs(c - np.cos(2 * np.pi * u2))) <= 1e-15
+    assert np.max(np.abs(s - np.sin(2 * np.pi * u2))) <= 1e-15
+    assert np.max(np.abs(c * c + s * s - 1.0)) <= 4.5e-16
+    # exact values: ln 1 = 0, ln 2^-k = -k ln 2 (one rounding), quarter turns
+    assert P.ln_unit(np.array([1.0]))[0] == 0.0
+    for k in (1, 2, 17, 53):
+        assert P.ln_unit(np.array([2.0 ** -k]))[0] == -k * P.LN2
+    c, s = P.cos_sin_turns(np.array([0.0, 0.25, 0.5, 0.75]))
+    assert np.array_equal(c, [1.0, 0.0, -1.0, 0.0]) and np.array_equal(s, [0.0, 1.0, 0.0, -1.0])
+    # the device generator holds the same constants
+    src = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "synth", "csrc", "synth_gen.hip")).read()
+    def table(name):
+        body = re.search(name + r"\[\d+\] = \{([^}]*)\}", src).group(1)
+        return tuple(float.fromhex(x) for x in re.findall(r"-?0x[0-9a-f.]+p[-+]\d+", body))
+    assert table("LOG_COEF") == P.LOG_COEF
+    assert table("SIN_COEF") == P.SIN_COEF
+    assert table("COS_COEF") == P.COS_COEF
+    for name in ("LN2", "HALF_PI", "SQRT_HALF"):
+        lit = re.search(r"constexpr double " + name + r" = (-?0x[0-9a-f.]+p[-+]\d+);", src).group(1)
+        assert float.fromhex(lit) == getattr(P, name)
+
+
 def test_normal_moments():
     n = 400_000
     z = normals(0, n, 3, 11, SEED_BASE)

@@ -460,6 +460,21 @@ def extra_ras(ctx, hmesh, spec, mats, F, G, restart, rtol=1e-10, subs=(1, 2, 4, 
     return out
 
 
+def device_ceilings(ctx):
+    """Measured ceilings (outside any timed region): MFMA loops of the
+    instructions the condensation issues, and a STREAM triad over 3 x 2 GiB."""
+    import torch
+    from paper_1605_01020_amd import api, F64, F32, BF16
+    out = {}
+    for name, prec in (("mfma_f64_tflops", F64), ("mfma_f32_tflops", F32), ("mfma_bf16_16x16x16_tflops", BF16)):
+        out[name], sink = api.probe_mfma(ctx, prec)
+        del sink
+    out["triad_gbps"], arrays = api.probe_triad(ctx)
+    del arrays
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -581,6 +596,10 @@ def main():
         del solver
         torch.cuda.empty_cache()
 
+    _log("device ceilings: MFMA loops and STREAM triad")
+    ceilings = device_ceilings(ctx)
+    _log(f"  {ceilings}")
+
     extras = {}
     if not args.no_extras:
         mats = (A, B, C, D)
@@ -611,6 +630,7 @@ def main():
     flops = condense_flops(n, t) * E
     peak = FP32_PEAK_TFLOPS if head == "mixed" else FP64_PEAK_TFLOPS
     achieved = flops / (r["condense_ms"] * 1e-3) / 1e12
+    measured_peak = ceilings["mfma_f32_tflops" if head == "mixed" else "mfma_f64_tflops"]
     traffic = None
     if head == "mixed" and dims == (16, 16, 8) and args.p == 3:
         traffic = measured_traffic(CONDENSE_SOURCES, "hbm_traffic_16x16x8_p3.md")
@@ -635,7 +655,9 @@ def main():
         "forms": results,
         "roofline": {"bound": "mfma", "kernel": "condense", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops,
+                     "measured_peak": measured_peak, "frac_of_measured": achieved / measured_peak},
+        "device_ceilings": ceilings,
     }
     out.update(extras)
     if "fp64" in results and "mixed" in results:

@@ -457,6 +457,26 @@ iedg_status iedg_mr_guess(iedg_context ctx, iedg_mr mr, const double* A, const d
                           const iedg_mr_opts* opts, double* alpha, double* z0, double* u0,
                           iedg_mr_info* info, hipStream_t stream);
 
+/* ---- measured device ceilings (the roofline report's second denominator) */
+/* An MFMA loop: n_wg workgroups of 512 threads, each wave issuing `iters`
+ * rounds of 8 independent 16x16 accumulations with the instruction the
+ * condensation issues for `prec` (IEDG_F64: FP64 16x16x4; IEDG_F32: FP32
+ * 16x16x4; IEDG_BF16: BF16 16x16x16 with FP32 accumulation) on operands of
+ * one.  sink (device, n_wg * 512 doubles) receives each thread's sum of its
+ * accumulators (8 chains of 4 entries), 32 K iters with K = 4 (FP64, FP32)
+ * or 16 (BF16), which checks that the loop ran; *flops (host) = 2 16 16 K 8 8 iters n_wg, the
+ * floating-point operations of the launch.  1 <= iters <= 2^20.
+ * Asynchronous on `stream` (time it with events on that stream). */
+iedg_status iedg_probe_mfma(iedg_context ctx, iedg_prec prec, int32_t n_wg,
+                            int32_t iters, double* sink, double* flops,
+                            hipStream_t stream);
+/* STREAM triad a = b + s c over n FP64 values (device arrays, n even and
+ * positive, 16-byte aligned; IEDG_ERR_INVALID_ARG otherwise): 24 n bytes of
+ * HBM traffic.  Asynchronous on `stream`. */
+iedg_status iedg_probe_triad(iedg_context ctx, int64_t n, const double* b,
+                             const double* c, double s, double* a,
+                             hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

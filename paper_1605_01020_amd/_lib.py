@@ -97,6 +97,8 @@ SIGNATURES = {
     "iedg_residual_full": (c_int32, [P, P, c_int32, P, P, P, P, P, P, P, P, P, P, P, P]),
     "iedg_residual_full_noalloc": (c_int32, [P, P, c_int32, P, P, P, P, P, P, P, P, P, P, P, P]),
     "iedg_axpy": (c_int32, [P, c_int64, c_double, P, P, P]),
+    "iedg_probe_mfma": (c_int32, [P, c_int32, c_int32, c_int32, P, ctypes.POINTER(c_double), P]),
+    "iedg_probe_triad": (c_int32, [P, c_int64, P, P, c_double, P, P]),
 }
 
 _lib = None

@@ -405,6 +405,45 @@ def axpy(ctx, alpha, x, y):
     return y
 
 
+def probe_mfma(ctx, prec, n_wg=2048, iters=2048, reps=3, sink=None):
+    """Measured MFMA ceiling for `prec` (iedg_probe_mfma): the best of `reps`
+    launches timed with events on the current stream.  Returns (TFLOP/s,
+    sink) -- sink holds each thread's accumulator sum, 32 K iters."""
+    sink = torch.empty(n_wg * 512, dtype=torch.float64, device="cuda") if sink is None else sink
+    flops = ctypes.c_double()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.check(ctx.L.iedg_probe_mfma(ctx.h, int(prec), n_wg, iters, _p(sink), ctypes.byref(flops), _stream()))
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return flops.value / (best * 1e-3) / 1e12, sink
+
+
+def probe_triad(ctx, n=1 << 28, s=3.0, reps=5, arrays=None):
+    """Measured HBM ceiling (iedg_probe_triad, a = b + s c over n doubles,
+    24 n bytes): the best of `reps` launches.  Returns (GB/s, (a, b, c))."""
+    if arrays is None:
+        b = torch.ones(n, dtype=torch.float64, device="cuda")
+        c = torch.full((n,), 0.5, dtype=torch.float64, device="cuda")
+        a = torch.empty_like(b)
+    else:
+        a, b, c = arrays
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.check(ctx.L.iedg_probe_triad(ctx.h, n, _p(b), _p(c), float(s), _p(a), _stream()))
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return 24.0 * n / (best * 1e-3) / 1e9, (a, b, c)
+
+
 class MinResGuess:
     """Minimal-residual Newton initial guess (iedg_mr_*, section 2.2.1,
     eq. MinRes2) for one mesh and element size, workspace for up to s_max

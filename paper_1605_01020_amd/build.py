@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # Longest compiles first: they start at once on the worker pool.
 IEDG_SOURCES = ["condense_f32.hip", "condense_bf16.hip", "condense_f32_single.hip", "condense_bf16_single.hip",
                 "condense_f64.hip", "condense_f64_single.hip", "sparse.hip", "context.hip", "condense.hip",
-                "mdf.hip", "ras.hip", "krylov.hip", "local.hip", "mr.hip"]
+                "mdf.hip", "ras.hip", "krylov.hip", "local.hip", "mr.hip", "probe.hip"]
 
 
 def _run(cmd):

@@ -249,9 +249,12 @@ struct SlabLoader {
   const int* sperm;
   int K;
 
-  __device__ __attribute__((always_inline)) inline void init(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K_) {
+  // k runs over [kb, kb + K_): the A operand's columns and the B operand's
+  // positions start at kb (folded into the base pointers)
+  __device__ __attribute__((always_inline)) inline void init(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K_,
+                                                             int kb = 0) {
     const int tid = threadIdx.x;
-    sperm = el.sperm;
+    sperm = el.sperm + kb;
     K = K_;
 #pragma unroll
     for (int q = 0; q < TL::AL; ++q) {
@@ -260,7 +263,7 @@ struct SlabLoader {
       ak[q] = 2 * (idx % (KC / 2));
       const int row = r0 + arow[q];
       aok[q] = row < rlim;
-      aptr[q] = aok[q] ? el.lrow(row) : el.LU;
+      aptr[q] = (aok[q] ? el.lrow(row) : el.LU) + kb;
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) {
@@ -382,10 +385,11 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
   }
 }
 
-// acc = in - L[r0:r0+TM, 0:K] * U[0:K, c0:c0+TN] for the workgroup's TM x TN
-// tile; rows >= rlim, cols >= clim and k >= K read as zero.  The accumulators
-// start from the input values (read while the first slabs are in flight) and
-// L enters the MFMAs negated.  Waves are stacked as described for Tile.
+// acc = in - L[r0:r0+TM, kb:kb+K] * U[kb:kb+K, c0:c0+TN] for the workgroup's
+// TM x TN tile (kb = 0 but for the update between the two halves of a
+// 128-wide panel); rows >= rlim, cols >= clim and k >= kb+K read as zero.
+// The accumulators start from the input values (read while the first slabs
+// are in flight) and L enters the MFMAs negated.  Waves are stacked as described for Tile.
 // k-slabs of KC go through two LDS stages; each thread keeps
 // the global loads of the next two slabs in flight in two register buffers.
 // Accumulators initialised with the tile's input values (zero outside
@@ -483,7 +487,7 @@ __device__ __attribute__((always_inline)) inline int tile_seg(int j0, int jl, in
 template <typename T, int TM, int TN, int MM = 0, bool HASW = false, bool COLS = (TM < TN)>
 __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& el, int r0, int rlim, int c0, int clim, int K, T* smem,
                                  typename Mfma<T>::acc_t (&acc)[Tile<T, TM, TN, COLS>::RB][Tile<T, TM, TN, COLS>::CB],
-                                 int seg = -1) {
+                                 int seg = -1, int kb = 0) {
   typedef Tile<T, TM, TN, COLS> TL;
   typedef Mfma<T> MF;
   typedef typename Pair<T>::v P2;
@@ -496,7 +500,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
   }
   const int nch = (K + KC - 1) / KC;
   SlabLoader<T, TM, TN, HASW, COLS> ld;
-  ld.init(el, r0, rlim, c0, clim, K);
+  ld.init(el, r0, rlim, c0, clim, K, kb);
   T* S0 = smem;
   T* S1 = smem + TL::STAGE;
   P2 a0[TL::AL], b0[TL::BL], a1[TL::AL], b1[TL::BL];
@@ -969,6 +973,86 @@ __device__ __attribute__((always_inline)) void panel_factor(const Elem<T>& el, i
   sync_global();  // the panel's stores are read by the panel-row GEMM
 }
 
+// The right half [cm, c1) of a 128-wide panel whose left half [c0, cm) is
+// factored (Linv holds L11^{-1} in its top-left block).  Factoring the two
+// halves separately, with one MFMA update between them, replaces the
+// left-looking updates of the right half's sub-panels from all 64 left
+// columns (each row's L values re-read from global once per sub-panel) by
+// one pass over them:
+//   (a) U[c0:cm, cm:c1] = L11^{-1} X[c0:cm, cm:c1]   (X staged in LDS)
+//   (b) X[cm:N, cm:c1] -= L[cm:N, c0:cm] U[c0:cm, cm:c1]   (256 x 64 tiles,
+//       k over [c0, cm); FP32 operands in every operand mode: within a
+//       panel the arithmetic stays that of the panel factorisation)
+//   (c) the right half by panel_factor, its L22^{-1} in the bottom-right
+//       block of Linv (pivoting among positions >= cm moves whole rows,
+//       their left-half L values with them)
+//   (d) the bottom-left block -L22^{-1} L21 L11^{-1}, with L21 = L[cm:c1,
+//       c0:cm] at the final positions.
+// sg: the GEMM staging area, free during the panel phase.
+template <typename T, int QA, int QC, int SW, int CT>
+__device__ __attribute__((always_inline)) void panel_right_half(const Elem<T>& el, int* sperm, int c0, int cm, int c1,
+                                                                const PanelBufs<T>& pb, T* sg, DeviceStatus* status,
+                                                                int elem) {
+  static_assert(CT == 128, "two halves of a 128-wide panel");
+  constexpr int H = 64, LS = CT + 1;
+  const int tid = threadIdx.x;
+  const int wl = cm - c0, wr = c1 - cm;  // wl == H, 0 < wr <= H
+  // (a)
+  {
+    T* X = sg;  // wl x H
+    for (int o = tid; o < wl * H; o += NT) {
+      const int i = o / H, j = o % H;
+      X[o] = j < wr ? el.ld(c0 + i, cm + j) : T(0);
+    }
+    __syncthreads();
+    for (int o = tid; o < wl * H; o += NT) {
+      const int i = o / H, j = o % H;
+      if (j < wr) {
+        T acc = T(0);
+        for (int m = 0; m <= i; ++m) acc += pb.Linv[i * LS + m] * X[m * H + j];
+        el.lrow(c0 + i)[cm + j] = acc;
+      }
+    }
+    sync_global();
+  }
+  // (b)
+  typedef Tile<T, 256, H> TH;
+  for (int r0 = cm; r0 < el.N; r0 += 256) {
+    typename Mfma<T>::acc_t acc[TH::RB][TH::CB];
+    gemm_tile<T, 256, H, 0>(el, r0, el.N, cm, c1, wl, sg, acc, 0, c0);
+    tile_store_seg<T, 256, H>(el, r0, el.N, cm, c1, acc, 0);
+  }
+  sync_global();
+  // (c)
+  PanelBufs<T> pr = pb;
+  pr.Linv = pb.Linv + wl * LS + wl;
+  panel_factor<T, QA, QC, SW, CT>(el, sperm, cm, c1, pr, status, elem);
+  // (d) Y = L21 L11^{-1} (L21 staged in LDS), then -L22^{-1} Y
+  {
+    T* L = sg;          // wr x H
+    T* Y = sg + H * H;  // wr x H
+    for (int o = tid; o < wr * H; o += NT) {
+      const int i = o / H, k = o % H;
+      L[o] = el.ld(cm + i, c0 + k);
+    }
+    __syncthreads();
+    for (int o = tid; o < wr * H; o += NT) {
+      const int i = o / H, k = o % H;
+      T acc = T(0);
+      for (int m = k; m < wl; ++m) acc += L[i * H + m] * pb.Linv[m * LS + k];
+      Y[o] = acc;
+    }
+    __syncthreads();
+    for (int o = tid; o < wr * H; o += NT) {
+      const int i = o / H, k = o % H;
+      T acc = T(0);
+      for (int m = 0; m <= i; ++m) acc += pb.Linv[(wl + i) * LS + wl + m] * Y[m * H + k];
+      pb.Linv[(wl + i) * LS + k] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
 // ---- the kernel -------------------------------------------------------------
 template <typename T, int CT>
 struct CondenseSmem {
@@ -1054,8 +1138,15 @@ __device__ __attribute__((always_inline)) void condense_one(const CondenseArgs<T
       tile_store_seg<T, SH::CM, CT>(el, r0, N, c0, c1, acc, 0);
     }
     sync_global();
-    // 2. factor the panel, growing L_pp^{-1}
-    panel_factor<T, QA, QC, LW, CT>(el, sperm, c0, c1, pb, a.status, e);
+    // 2. factor the panel, growing L_pp^{-1} (a 128-wide panel in two
+    //    halves of 64 with one MFMA update between them)
+    if constexpr (CT == 128) {
+      const int cm = min(c0 + 64, c1);
+      panel_factor<T, QA, QC, LW, CT>(el, sperm, c0, cm, pb, a.status, e);
+      if (cm < c1) panel_right_half<T, QA, QC, LW, CT>(el, sperm, c0, cm, c1, pb, sg, a.status, e);
+    } else {
+      panel_factor<T, QA, QC, LW, CT>(el, sperm, c0, c1, pb, a.status, e);
+    }
     // the leaves write L_pp^{-1} on and below the diagonal of each 8-row
     // strip only; the triangular solve below reads whole 16 x 16 diagonal
     // blocks, so clear the strictly upper part (and the padding of a

@@ -547,6 +547,14 @@ def test_condense_widths(ctx, p, prec):
                 assert rel(ke, Ke) <= 1e-12 and rel(rr, re) <= 1e-12
             elif prec == 1:
                 assert rel(ke, Ke) <= 2e-5 and rel(rr, re) <= 2e-5
+                if e == 0:
+                    # the retained factors: A[perm] = L U (L unit lower, rows stored
+                    # at their physical row), from every panel and panel half
+                    perm = fac["perm"][e].cpu().numpy()
+                    F = fac["LU"][e].double().cpu().numpy()[perm]
+                    Lf = np.tril(F, -1) + np.eye(spec.n)
+                    assert rel(Lf @ np.triu(F), blocks[e]["A"][perm]) <= 2e-5
+                    assert np.array_equal(np.sort(perm), np.arange(spec.n))
             else:
                 corr = np.linalg.norm(blocks[e]["D"] - Ke)
                 assert np.linalg.norm(ke - Ke) <= 2.0 ** -6 * corr + 2e-5 * np.linalg.norm(Ke)

@@ -739,15 +739,171 @@ __global__ __launch_bounds__(256) void ilu0_small_kernel(int nrows, const int32_
   if (!ok) latch_status(status, IEDG_ERR_SINGULAR, i);
 }
 
+// The same factorisation with the row's blocks staged in LDS: one wave per
+// block row (one row a workgroup).  Every slot of row i (A_ik, the updated
+// A_ij, the pivot block) lives in LDS from the first read to the final
+// write-back, so the chain of lower slots runs without the global stores,
+// waits and cache invalidations between slots; only U_kk^{-1} and U_kj
+// (rows of earlier levels) come from global memory, one slot ahead as in
+// ilu0_small_kernel.  The arithmetic is that kernel's, operation for
+// operation.  Dynamic LDS: the longest row of the level, in blocks.
+template <typename T, int B>
+__global__ __launch_bounds__(64) void ilu0_small_lds_kernel(const int32_t* __restrict__ rows,
+                                                            const int32_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ diag_slot,
+                                                            const int32_t* __restrict__ lptr,
+                                                            const int32_t* __restrict__ lslot,
+                                                            const int32_t* __restrict__ uptr,
+                                                            const int32_t* __restrict__ upd, T* M,
+                                                            DeviceStatus* status) {
+  constexpr int BB = B * B;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* R = reinterpret_cast<T*>(lds_raw);
+  const int lane = threadIdx.x;
+  const int i = rows[blockIdx.x];
+  const int s0 = row_ptr[i], nv = (row_ptr[i + 1] - s0) * BB;
+  const T* Mrow = M + (size_t)s0 * BB;
+  for (int q = lane; q < nv; q += 64) R[q] = Mrow[q];
+  const int l0 = lptr[i], l1 = lptr[i + 1];
+  T un[BB], ukn[BB];
+  if (l0 < l1) {
+    small_load<T, B>(M + (size_t)lslot[2 * l0 + 1] * BB, un);
+    const int x0 = uptr[l0] + lane;
+    if (x0 < uptr[l0 + 1]) small_load<T, B>(M + (size_t)upd[2 * x0] * BB, ukn);
+  }
+  __syncthreads();
+  for (int l = l0; l < l1; ++l) {
+    const int sik = lslot[2 * l] - s0;
+    const int xb = uptr[l], xe = uptr[l + 1];
+    T a[BB], u[BB], L[BB], uk0[BB], c0[BB];
+    small_load<T, B>(R + sik * BB, a);
+    if (xb + lane < xe) small_load<T, B>(R + (upd[2 * (xb + lane) + 1] - s0) * BB, c0);
+#pragma unroll
+    for (int q = 0; q < BB; ++q) {
+      u[q] = un[q];
+      uk0[q] = ukn[q];
+    }
+    if (l + 1 < l1) {
+      small_load<T, B>(M + (size_t)lslot[2 * (l + 1) + 1] * BB, un);
+      const int x1 = xe + lane;
+      if (x1 < uptr[l + 2]) small_load<T, B>(M + (size_t)upd[2 * x1] * BB, ukn);
+    }
+    small_mm<T, B, false>(a, u, L);
+    if (xb + lane < xe) {
+      small_mm<T, B, true>(L, uk0, c0);
+      T* C = R + (upd[2 * (xb + lane) + 1] - s0) * BB;
+#pragma unroll
+      for (int q = 0; q < BB; ++q) C[q] = c0[q];
+    }
+    for (int x = xb + lane + 64; x < xe; x += 64) {
+      T* C = R + (upd[2 * x + 1] - s0) * BB;
+      T ukj[BB], c[BB];
+      small_load<T, B>(M + (size_t)upd[2 * x] * BB, ukj);
+      small_load<T, B>(C, c);
+      small_mm<T, B, true>(L, ukj, c);
+#pragma unroll
+      for (int q = 0; q < BB; ++q) C[q] = c[q];
+    }
+    // every lane has read A_ik (into a) before lane 0 replaces it by L_ik;
+    // the updates of this slot are visible before the next slot reads
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < BB; ++q) R[sik * BB + q] = L[q];
+    __syncthreads();
+  }
+  if (lane == 0) {
+    T* Dg = R + (diag_slot[i] - s0) * BB;
+    T W[B][B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) W[r][c] = Dg[c * B + r];
+    bool piv[B];
+    int step[B], prow[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      piv[r] = false;
+      step[r] = 0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      int p = -1;
+      double best = -1.0;
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        const double v = fabs((double)W[r][k]);
+        if (!piv[r] && (p < 0 || v > best)) {
+          best = v;
+          p = r;
+        }
+      }
+      if (!(best > 0.0) || !(best <= DBL_MAX)) ok = false;
+      T pr[B];
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        T v = W[0][c];
+#pragma unroll
+        for (int r = 1; r < B; ++r) v = r == p ? W[r][c] : v;
+        pr[c] = v;
+      }
+      const T ip = T(1) / pr[k];
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        if (r == p) {
+#pragma unroll
+          for (int c = 0; c < B; ++c) W[r][c] = c == k ? ip : -(pr[c] * ip);
+          piv[r] = true;
+          step[r] = k;
+        } else {
+          const T v = W[r][k];
+#pragma unroll
+          for (int c = 0; c < B; ++c) W[r][c] = c == k ? v * ip : W[r][c] - v * (pr[c] * ip);
+        }
+      }
+      prow[k] = p;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c < B; ++c) Dg[prow[c] * B + step[r]] = W[r][c];
+    if (!ok) latch_status(status, IEDG_ERR_SINGULAR, i);
+  }
+  __syncthreads();
+  T* Mw = M + (size_t)s0 * BB;
+  for (int q = lane; q < nv; q += 64) Mw[q] = R[q];
+}
+
+// LDS a workgroup of ilu0_small_lds_kernel may take (the rest of the CU's
+// 160 KiB stays for other rows of the level).
+constexpr size_t kSmallRowLds = 96 * 1024;
+
 template <typename T, int B>
 static iedg_status factor_levels_small(iedg_context ctx, iedg_mesh m, T* M, hipStream_t stream) {
   auto kern = ilu0_small_kernel<T, B>;
+  auto kern_lds = ilu0_small_lds_kernel<T, B>;
+  const size_t blk = sizeof(T) * B * B;
+  IEDG_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(kern_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallRowLds));
   for (int l = 0; l < m->n_levels; ++l) {
     const int r0 = m->level_ptr[l], cnt = m->level_ptr[l + 1] - r0;
     if (cnt == 0) continue;
-    hipLaunchKernelGGL(kern, dim3((cnt + 3) / 4), dim3(256), 0, stream, cnt,
-                       m->d_level_rows + r0, m->d_diag_slot, m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd,
-                       M, ctx->d_status);
+    // the longest row of the level decides the LDS of every workgroup
+    int len = 0;
+    for (int r = r0; r < r0 + cnt; ++r) {
+      const int i = m->level_rows[r];
+      len = std::max(len, m->row_ptr[i + 1] - m->row_ptr[i]);
+    }
+    const size_t lds = blk * (size_t)len;
+    if (lds <= kSmallRowLds) {
+      hipLaunchKernelGGL(kern_lds, dim3(cnt), dim3(64), lds, stream, m->d_level_rows + r0, m->d_row_ptr,
+                         m->d_diag_slot, m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr, m->d_ilu_upd, M, ctx->d_status);
+    } else {
+      hipLaunchKernelGGL(kern, dim3((cnt + 3) / 4), dim3(256), 0, stream, cnt,
+                         m->d_level_rows + r0, m->d_diag_slot, m->d_ilu_lptr, m->d_ilu_l, m->d_ilu_uptr,
+                         m->d_ilu_upd, M, ctx->d_status);
+    }
     IEDG_LAUNCH_CHECK(ctx, "ilu0 small level launch");
   }
   return IEDG_OK;

@@ -194,10 +194,13 @@ def serving_sweep(ctx, fracs, n_warm, n_meas, slots, budget_gb, n_cap=None, log=
                  restart=wl.restart, tol=wl.rtol)
     out = {"simulations": len(wl.meshes), "slots": slots, "budget_gb": budget_gb,
            "static_gb": srv.static_bytes / 1e9}
+    def progress(k, total):
+        log(f"  {k}/{total} requests done")
+
     reqs = poisson_requests(wl.seed, n_warm + n_cap, 1e6, len(wl.meshes))
-    srv.run(reqs[:n_warm], real_time=False)
+    srv.run(reqs[:n_warm], real_time=False, progress=progress)
     t0 = time.perf_counter()
-    done = srv.run(reqs[n_warm:], real_time=False)
+    done = srv.run(reqs[n_warm:], real_time=False, progress=progress)
     cap = len(done) / (time.perf_counter() - t0)
     out["capacity_solves_per_s"] = cap
     out["capacity_hit_rate"] = sum(1 for r in done if r.hit) / len(done)
@@ -207,7 +210,7 @@ def serving_sweep(ctx, fracs, n_warm, n_meas, slots, budget_gb, n_cap=None, log=
         rate = frac * cap
         reqs = poisson_requests(wl.seed + 1 + i, n_warm + n_meas, rate, len(wl.meshes))
         t0 = time.perf_counter()
-        done = srv.run(reqs, real_time=True)
+        done = srv.run(reqs, real_time=True, progress=progress)
         elapsed = time.perf_counter() - t0
         meas = [r for r in done if r.rid >= n_warm]
         span = max(r.done for r in meas) - min(r.arrival for r in meas)
@@ -229,7 +232,8 @@ def bench_serving(args):
     ctx = api.Context(0)
     apply_tuning(ctx)
     fracs = [float(f) for f in args.loads.split(",")]
-    res = serving_sweep(ctx, fracs, args.serve_warmup, args.requests, args.slots, args.budget_gb)
+    res = serving_sweep(ctx, fracs, args.serve_warmup, args.requests, args.slots, args.budget_gb,
+                        n_cap=args.capacity_requests)
     head = res["load"][f"{fracs[len(fracs) // 2]:.1f}"]
     line = {
         "metric": "Newton-step solves/s at relative residual 1e-8 with p50/p99 latency, serving form",
@@ -238,7 +242,8 @@ def bench_serving(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic (seeded Poisson arrivals and Philox matrices)",
         "config": {"workload": f"{res['simulations']} simulations from the uneven batch distribution, Poisson "
-                               f"arrivals at {fracs} x measured capacity, {args.serve_warmup} warm-up + "
+                               f"arrivals at {fracs} x measured capacity ({args.capacity_requests} closed-loop "
+                               f"requests), {args.serve_warmup} warm-up + "
                                f"{args.requests} measured requests per load, budget {args.budget_gb} GB, "
                                f"{args.slots} stream slots"},
         "serving": res,
@@ -494,6 +499,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="serving: warm-up requests per load")
     ap.add_argument("--loads", default="0.5,0.7,0.9", help="serving: arrival rates as fractions of capacity")
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--capacity-requests", type=int, default=500,
+                    help="serving: closed-loop requests that measure capacity")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="first run a plain device copy of this many GiB (reference for HBM counters)")
     args = ap.parse_args()

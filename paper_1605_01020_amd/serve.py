@@ -237,9 +237,10 @@ class Server:
         slot.event = slot.req = None
 
     # -- the loop ---------------------------------------------------------------
-    def run(self, requests, real_time=True):
+    def run(self, requests, real_time=True, progress=None, every=250):
         """Serve `requests` (sorted by arrival).  real_time: arrivals follow
-        the wall clock; otherwise every request is available at once."""
+        the wall clock; otherwise every request is available at once.
+        progress(done, total) is called after every `every` completions."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = []
         done = []
@@ -255,6 +256,8 @@ class Server:
                     self._complete(slot, time.perf_counter() - self._t0)
                     done.append(r)
                     progressed = True
+                    if progress is not None and len(done) % every == 0:
+                        progress(len(done), len(requests))
             for slot in self.slots:
                 if slot.req is not None:
                     continue

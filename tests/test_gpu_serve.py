@@ -39,10 +39,10 @@ CASES = [MeshCase(0, (2, 2, 1), 1), MeshCase(1, (2, 1, 1), 2), MeshCase(2, (1, 1
          MeshCase(6, (2, 1, 1), 3), MeshCase(7, (1, 2, 1), 4)]
 
 
-def _serve(ctx, requests, n_slots, budget):
+def _serve(ctx, requests, n_slots, budget, progress=None):
     from paper_1605_01020_amd.serve import Server
     srv = Server(ctx, CASES, SEED, budget_bytes=budget, n_slots=n_slots, keep_results=True)
-    done = srv.run(requests, real_time=False)
+    done = srv.run(requests, real_time=False, progress=progress, every=5)
     stats = dict(srv.stats)
     srv.close()
     return {(r.sim, r.rhs): r for r in done}, stats
@@ -60,7 +60,9 @@ def test_serving_mix_invariance(ctx):
     # room for the largest simulation and a fifth of it: admitting the p = 4
     # simulation evicts the others, and the p = 3 one cannot stay beside it
     tight = 1.2 * max(Simulation.footprint(c) for c in CASES)
-    mixed, st_mix = _serve(ctx, reqs, 4, tight)
+    calls = []
+    mixed, st_mix = _serve(ctx, reqs, 4, tight, progress=lambda k, n: calls.append((k, n)))
+    assert calls == [(k, 24) for k in range(5, 25, 5)]  # every 5 completions
     assert st_mix["evictions"] > 0 and st_mix["misses"] > st_alone["misses"]
     assert set(alone) == set(mixed) and len(alone) == 24
     for key, a in alone.items():

@@ -235,7 +235,26 @@ struct Tile {
 // flight and the wait before storing a slab covers only that slab's loads:
 // the next slab's loads stay in flight behind the MFMA work.  HASW: the
 // tile includes the right-hand-side column (w, FP64 storage).
-template <typename T, int TM, int TN, bool HASW, bool COLS = (TM < TN)>
+// Round to nearest even FP32 -> BF16 (bit pattern); NaN stays NaN.
+__device__ __attribute__((always_inline)) inline short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// A slab value as it enters LDS: unchanged (MM = 0), or rounded once to
+// BF16 and kept as the FP32 value with those upper 16 bits (MM = 1), so
+// that a fragment read takes the upper half without rounding again.
+template <int MM, typename T>
+__device__ __attribute__((always_inline)) inline T slab_value(T v) {
+  if constexpr (MM == 0) {
+    return v;
+  } else {
+    return __uint_as_float((unsigned)(unsigned short)to_bf16(v) << 16);
+  }
+}
+
+template <typename T, int TM, int TN, bool HASW, bool COLS = (TM < TN), int MM = 0>
 struct SlabLoader {
   typedef Tile<T, TM, TN, COLS> TL;
   typedef typename Pair<T>::v P2;
@@ -310,8 +329,8 @@ struct SlabLoader {
       // L enters negated: the accumulators start from the tile's input
       // values, so the MFMA chain computes in - L U directly
       const bool ok = aok[q] && k0 + ak[q] < K;
-      As[ak[q] * TL::SA + arow[q]] = ok ? -va[q].x : T(0);
-      As[(ak[q] + 1) * TL::SA + arow[q]] = ok ? -va[q].y : T(0);
+      As[ak[q] * TL::SA + arow[q]] = ok ? slab_value<MM>(-va[q].x) : T(0);
+      As[(ak[q] + 1) * TL::SA + arow[q]] = ok ? slab_value<MM>(-va[q].y) : T(0);
     }
 #pragma unroll
     for (int q = 0; q < TL::BL; ++q) {
@@ -322,22 +341,17 @@ struct SlabLoader {
       if constexpr (HASW) {
         if (isw[q]) r.x = ok ? (T)vw[q] : T(0);
       }
+      r.x = slab_value<MM>(r.x);
+      r.y = slab_value<MM>(r.y);
       *reinterpret_cast<P2*>(Bs + bk[q] * TL::SB + bcol[q]) = r;
     }
   }
 };
 
-// Round to nearest even FP32 -> BF16 (bit pattern); NaN stays NaN.
-__device__ __attribute__((always_inline)) inline short to_bf16(float f) {
-  const unsigned u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 
-// MM = 0: MFMA in T.  MM = 1 (T = float): operands rounded to BF16, FP32
-// accumulation, v_mfma_f32_16x16x16_bf16 (A operand: lane l holds
+// MM = 0: MFMA in T.  MM = 1 (T = float): operands rounded to BF16 (when
+// they entered the slab), FP32 accumulation, v_mfma_f32_16x16x16_bf16 (A operand: lane l holds
 // A[l % 16][4 (l / 16) + i], B operand: B[4 (l / 16) + i][l % 16], i < 4;
 // accumulator as for the FP32 16x16x4 operation).
 template <typename T, int TM, int TN, int MM, bool COLS = (TM < TN)>
@@ -371,11 +385,11 @@ __device__ __attribute__((always_inline)) inline void slab_mma(const T* stage, i
 #pragma unroll
       for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) av[rb][i] = to_bf16(As[(16 * ks + i) * TL::SA + 16 * rb]);
+        for (int i = 0; i < 4; ++i) av[rb][i] = (short)(__float_as_uint(As[(16 * ks + i) * TL::SA + 16 * rb]) >> 16);
 #pragma unroll
       for (int cb = 0; cb < TL::CB; ++cb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bv[cb][i] = to_bf16(Bs[(16 * ks + i) * TL::SB + 16 * cb]);
+        for (int i = 0; i < 4; ++i) bv[cb][i] = (short)(__float_as_uint(Bs[(16 * ks + i) * TL::SB + 16 * cb]) >> 16);
 #pragma unroll
       for (int rb = 0; rb < TL::RB; ++rb)
 #pragma unroll
@@ -499,7 +513,7 @@ __device__ __attribute__((always_inline)) inline void gemm_tile(const Elem<T>& e
     return;
   }
   const int nch = (K + KC - 1) / KC;
-  SlabLoader<T, TM, TN, HASW, COLS> ld;
+  SlabLoader<T, TM, TN, HASW, COLS, MM> ld;
   ld.init(el, r0, rlim, c0, clim, K, kb);
   T* S0 = smem;
   T* S1 = smem + TL::STAGE;

@@ -1,7 +1,8 @@
 #pragma once
 // Element static condensation on gfx950 (section 2.2.1, eq. LS): the kernel.
-// Included by one translation unit per precision (condense_f64.hip,
-// condense_f32.hip, condense_bf16.hip), so they compile in parallel.
+// Included by two translation units per precision (condense_<p>.hip: the
+// persistent batched form; condense_<p>_single.hip: one element per
+// workgroup), so they compile in parallel.
 //
 // Per element the bordered matrix  M = [A B F; C D 0]  (N = n + t rows,
 // NC = N + 1 columns with F) is reduced by n steps of Gaussian elimination
@@ -14,18 +15,22 @@
 // physical row perm[i] of every A-row-indexed array (A itself, LU, U12, w),
 // and only the permutation in LDS is updated when a pivot is chosen.
 //
-// Schedule, one 512-thread workgroup (8 waves) per element, 64-wide panels:
+// Schedule, one 512-thread workgroup (8 waves) per element, panels of CT =
+// 64 or (FP32 storage) 128 columns:
 //   for each panel [c0, c1):
 //     1. panel column (Crout order): M[c0:, c0:c1] = in - L[c0:, :c0] U[:c0, c0:c1]
-//        -- MFMA tiles of 256 x 64 fed from double-buffered LDS k-slabs
+//        -- MFMA tiles of 256 x CT fed from double-buffered LDS k-slabs
 //     2. panel factorisation in register-resident sub-panels of 16 (or 8)
 //        columns: each sub-panel first takes the updates of the panel's
 //        earlier sub-panels (left-looking), then partial pivoting with one
 //        workgroup barrier per column; the panel's L^{-1} is grown in LDS
+//        (a 128-wide panel in two halves of 64 with one MFMA update between)
 //     3. panel row: U[c0:c1, c1:] = L_pp^{-1} (in - L[c0:c1, :c0] U[:c0, c1:])
-//        -- MFMA tiles of 64 x 256; the triangular solve with L_pp^{-1} is a
+//        -- MFMA tiles of CT x 256; the triangular solve with L_pp^{-1} is a
 //        second MFMA pass on the accumulators (each wave owns whole columns)
 //   4. Schur block: M[n:, n:] = in - L21 U12 (MFMA, K = n)
+// BF16 operand mode: the GEMM operands are rounded to BF16 once, as they
+// enter the LDS slab; accumulation, panels and storage stay FP32.
 #include <algorithm>
 #include <climits>
 
